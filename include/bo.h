@@ -1,0 +1,206 @@
+/* bo.h -- C ABI of the MI355X (gfx950) Gaussian-process surrogate step for
+ * Bayesian-optimization auto-tuning over a discrete, constrained search space.
+ *
+ * Method: Willemsen, van Nieuwpoort, van Werkhoven, "Bayesian Optimization for
+ * auto-tuning GPU kernels" (arXiv 2111.14991).  One step, after each new
+ * observation:
+ *   fit      K_nn = amp * Matern(|x_i - x_j| / l) + delta I, L L^T = K_nn (FP64),
+ *            alpha = K_nn^-1 (y - m), m = mean(y)            (Section III-B)
+ *   predict  mu(x) = m + k*^T alpha, var(x) = amp - |L^-1 k*|^2 clamped at 0,
+ *            for every valid, not yet evaluated candidate  (Sections III-D.2, III-G)
+ *   acquire  EI, PI, LCB in minimization form with one exploration factor
+ *            lambda, constant or contextual-variance          (Sections III-C, III-F)
+ *   select   argmax EI, argmax PI, argmin LCB over those candidates.
+ *
+ * Conventions for every call:
+ *  - Ownership: the caller owns all buffers.  Pointers marked "device" are
+ *    device memory on the current HIP device; "host" pointers are ordinary
+ *    host memory.  The library never frees caller memory.  The workspace
+ *    passed to bo_session_create holds all per-session device state; the
+ *    library allocates only a small host-side handle and one pinned host
+ *    result record at creation, and nothing afterwards.
+ *  - Indices: 0-based int64 into the caller's enumeration of the candidate set
+ *    (restriction-pruned points included).
+ *  - Ordering: all device work is enqueued on the session stream in call
+ *    order.  Calls documented as synchronizing wait for that stream.
+ *  - Errors: every call returns a bo_status; no exception crosses the ABI.
+ *    Host-checkable arguments are validated before anything is enqueued.
+ *    Errors found on the device (an observation index of an invalid point, a
+ *    non-finite y, an exhausted jitter schedule) are reported by the next
+ *    synchronizing call.  bo_last_error() returns a thread-local message for
+ *    the last failing call on that thread.
+ *  - Threads: one session must not be used from two threads at once.
+ */
+#ifndef BO_MI355X_H
+#define BO_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BO_OK = 0,
+  BO_E_INVALID_ARG = 1,  /* bad argument (host check) or bad observation data (device check) */
+  BO_E_NOT_PD = 2,       /* K_nn not positive definite for any jitter of the schedule */
+  BO_E_NO_CANDIDATE = 3, /* every candidate is restriction-pruned or already evaluated */
+  BO_E_WORKSPACE = 4,    /* workspace too small or misaligned */
+  BO_E_HIP = 5,          /* a HIP runtime call failed */
+  BO_E_STATE = 6,        /* call out of order (no candidates set, no fit, n = 0, ...) */
+  BO_E_BUDGET = 7,       /* serving memory budget below one session */
+  BO_E_NUMERIC = 8       /* a NaN acquisition value was met */
+} bo_status;
+
+/* Arithmetic of the posterior (the fit is FP64 in every mode).
+ *  BO_FP64   : cross-covariance, variance contraction and mean in FP64.
+ *  BO_FP32   : cross-covariance and mean in FP64; variance contraction on FP32
+ *              matrix cores over chunks of 16 observations, chunks summed in FP64.
+ *  BO_BF16X3 : cross-covariance in FP32, split into bfloat16 high and low parts;
+ *              variance contraction as three bfloat16 matrix-core products
+ *              (hi*hi + hi*lo + lo*hi) with FP32 accumulation; mean in FP64
+ *              from the FP32 covariances. */
+typedef enum { BO_FP64 = 0, BO_FP32 = 1, BO_BF16X3 = 2 } bo_precision;
+
+/* Acquisition-function bits (Section III-C). */
+enum { BO_EI = 1, BO_POI = 2, BO_LCB = 4 };
+
+/* Problem size fixed for a session's lifetime. */
+typedef struct {
+  int64_t N;         /* candidates in the caller's enumeration, 1 <= N < 2^31 */
+  int32_t d;         /* parameters (dimensions), 1 <= d <= 16 */
+  int32_t n_max;     /* most observations a fit will hold, 1 <= n_max <= 1024 */
+  int32_t precision; /* bo_precision */
+  int32_t reserved;
+} bo_problem;
+
+/* Surrogate hyperparameters (Section III-B: fixed lengthscale, no marginal-
+ * likelihood search).  Defaults: nu2 = 5, lengthscale = 1, amp = 1,
+ * noise = 1e-6, jitter_tries = 7. */
+typedef struct {
+  int32_t nu2;          /* 3 or 5: Matern nu = nu2 / 2 */
+  int32_t jitter_tries; /* 1..20: attempts of the diagonal-addition schedule */
+  double lengthscale;   /* > 0, in normalized coordinates */
+  double amp;           /* prior variance k(0) > 0 */
+  double noise;         /* >= 0, added to the diagonal of K_nn; attempt t >= 1 adds
+                           max(noise, 1e-10 amp) * 10^t instead */
+} bo_gp_params;
+
+/* Exploration factor (Section III-F). */
+typedef struct {
+  int32_t mode;        /* 0: lambda = lambda_const; 1: contextual variance
+                          lambda = (var_mean / (mu_s / f_best)) / var_s_mean */
+  uint32_t acq_bits;   /* BO_EI | BO_POI | BO_LCB (0 means all three) */
+  double lambda_const; /* mode 0 (the paper's constant is 0.01) */
+  double mu_s;         /* mode 1: mean of the initial sample's observations, > 0 */
+  double var_s_mean;   /* mode 1: mean posterior variance after the initial sample;
+                          <= 0 means "this step is that one" (lambda = f_best/mu_s) */
+} bo_acq_params;
+
+/* Result of one step.  Slots: [0] EI (argmax), [1] PI (argmax), [2] LCB
+ * (argmin).  Ties go to the lowest index.  A slot whose function was not
+ * requested, or with no candidate, holds idx -1 and a NaN score. */
+typedef struct {
+  int64_t idx[3];
+  double score[3];
+  double lambda;     /* exploration factor used */
+  double var_mean;   /* mean posterior variance over the predicted candidates */
+  double jitter;     /* diagonal addition accepted by the fit */
+  double f_best;     /* incumbent: minimum observed y */
+  double mean_y;     /* prior mean m */
+  int64_t n_unmasked;/* candidates predicted (valid and not evaluated) */
+  int32_t status;    /* bo_status of the step */
+  int32_t n_obs;     /* observations in the fit */
+} bo_acq_result;
+
+/* Fit diagnostics. */
+typedef struct {
+  int32_t status;
+  int32_t n;
+  int32_t attempt;   /* index of the accepted jitter attempt */
+  int32_t reserved;
+  double jitter, mean_y, f_best;
+} bo_fit_info;
+
+typedef struct bo_session bo_session;
+
+/* Library version string (static storage). */
+const char* bo_version(void);
+
+/* Thread-local message of the last failing call on this thread ("" if none).
+ * Valid until the next failing call on the same thread. */
+const char* bo_last_error(void);
+
+/* Device workspace bytes a session of this problem needs (256-byte aligned
+ * start required).  Returns BO_E_INVALID_ARG for sizes outside the limits. */
+bo_status bo_workspace_query(const bo_problem* prob, size_t* bytes);
+
+/* Create a session over a caller-owned device workspace (>= the queried size)
+ * and a hipStream_t (passed as void*; NULL = the default stream).  gp may be
+ * NULL for the defaults.  The handle is freed by bo_session_destroy. */
+bo_status bo_session_create(bo_session** out, const bo_problem* prob, const bo_gp_params* gp,
+                            void* workspace, size_t bytes, void* stream);
+
+/* Waits for the session stream, then releases the handle (not the workspace). */
+void bo_session_destroy(bo_session* s);
+
+/* Change the stream later calls enqueue on. */
+bo_status bo_session_set_stream(bo_session* s, void* stream);
+
+/* Candidate set as a discrete grid (Section III-D): parameter j has
+ * levels[j] >= 1 ordered values (host array of d entries); candidate c is grid
+ * point cand[c] (device int64 array of N entries, row-major grid index, last
+ * parameter fastest), or grid point c when cand is NULL (then N must equal the
+ * grid size).  Each parameter is normalized linearly, level i -> i / (k - 1)
+ * (Section III-D.1).  invalid (device uint8[N], nonzero = restriction-pruned;
+ * NULL = none) marks points never to predict or select (Section III-D.2).
+ * Valid candidates are compacted once, keeping their original indices.
+ * Synchronizing; *n_valid (host, nullable) receives the valid count.
+ * Errors: BO_E_INVALID_ARG (bad levels, grid index out of range). */
+bo_status bo_set_grid(bo_session* s, const int32_t* levels, const int64_t* cand,
+                      const uint8_t* invalid, int64_t* n_valid);
+
+/* Candidate set from coordinates already normalized by the caller: X is a
+ * device N x d row-major array, FP64 (x_is_f32 = 0) or FP32 (x_is_f32 = 1).
+ * Otherwise as bo_set_grid. */
+bo_status bo_set_candidates(bo_session* s, const void* X, int32_t x_is_f32,
+                            const uint8_t* invalid, int64_t* n_valid);
+
+/* Refit on n valid observations (Section III-B): obs_idx (device int64[n],
+ * candidate indices, each of a valid candidate) and y (device double[n],
+ * finite), in observation order; 1 <= n <= n_max.  Computes m = mean(y),
+ * f_best = min(y), the FP64 Cholesky factor of K_nn with the jitter schedule
+ * (pivots must exceed n 2^-52 times their diagonal entry), L^-1 and alpha.
+ * Asynchronous; device-side errors surface at the next synchronizing call. */
+bo_status bo_gp_fit(bo_session* s, const int64_t* obs_idx, const double* y, int32_t n);
+
+/* Synchronizing: fit status, accepted jitter, m and f_best.  alpha (host
+ * double[n]) and Linv (host double[n*n], row-major lower triangle of L^-1)
+ * are filled when non-NULL. */
+bo_status bo_fit_read(bo_session* s, bo_fit_info* info, double* alpha, double* Linv);
+
+/* Posterior over the candidates that are valid and not visited (device
+ * uint8[N], nonzero = evaluated; NULL = none).  mu and var (device double[N],
+ * nullable) receive the mean and latent variance, NaN where excluded.
+ * var_mean (host, nullable) receives the mean variance; when it is non-NULL
+ * the call is synchronizing. */
+bo_status bo_posterior(bo_session* s, const uint8_t* visited, double* mu, double* var,
+                       double* var_mean);
+
+/* Whole step after bo_gp_fit: posterior, lambda, acquisitions and the masked
+ * arg-optimum (Sections III-C, III-D.2, III-F, III-G).  Synchronizing: *out
+ * (host) receives the result; the return value equals out->status. */
+bo_status bo_acquire(bo_session* s, const uint8_t* visited, const bo_acq_params* params,
+                     bo_acq_result* out);
+
+/* Same as bo_acquire without waiting: *out_dev (device) is written on the
+ * session stream.  Jitter escalation of a large fit (n > 256) is not retried
+ * on this path; out_dev->status reports BO_E_NOT_PD instead. */
+bo_status bo_acquire_async(bo_session* s, const uint8_t* visited, const bo_acq_params* params,
+                           bo_acq_result* out_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,440 @@
+// C ABI of the BO-step library: argument validation, workspace carving,
+// session lifecycle and the launch sequence of one step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "bo_internal.h"
+
+using namespace bo;
+
+namespace bo {
+int64_t acquire_blocks(int64_t n_valid);
+}
+
+struct bo_session {
+  bo_problem prob;
+  GpConst gp;
+  Layout lo;
+  DevPtrs P;
+  hipStream_t stream;
+  uint8_t* ws;
+  size_t ws_bytes;
+  int64_t n_valid;
+  int have_cand;
+  int have_fit;
+  int n;
+  int fit_attempt;
+  bo_acq_result* hres;  // pinned host copy of the device result
+  DevState* hstate;     // pinned host copy of the device state
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+bo_status fail(bo_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(BO_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+bool problem_ok(const bo_problem* p) {
+  return p && p->N >= 1 && p->N < (int64_t(1) << 31) && p->d >= 1 && p->d <= kMaxD && p->n_max >= 1 &&
+         p->n_max <= kMaxN && p->precision >= BO_FP64 && p->precision <= BO_BF16X3;
+}
+
+__global__ void k_state_clear(DevState* st, int full) {
+  if (threadIdx.x == 0) {
+    if (full) {
+      DevState z{};
+      z.status = BO_E_STATE;
+      *st = z;
+    } else {
+      st->post_status = BO_OK;
+      st->n_unmasked = 0;
+    }
+  }
+}
+
+bo_status sync_state(bo_session* s) {
+  HIP_TRY(hipMemcpyAsync(s->hstate, s->P.st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return BO_OK;
+}
+
+// Large fits retry the jitter schedule from the host after a pivot failure.
+bo_status settle_fit(bo_session* s, bool* retried) {
+  *retried = false;
+  bo_status rc = sync_state(s);
+  if (rc != BO_OK) return rc;
+  while (s->hstate->status == BO_E_NOT_PD && s->hstate->need_retry && s->n > kSmallFitMax) {
+    s->fit_attempt += 1;
+    HIP_TRY(launch_fit_large(s->P, s->lo, s->gp, nullptr, nullptr, s->n, s->fit_attempt, s->stream));
+    rc = sync_state(s);
+    if (rc != BO_OK) return rc;
+    *retried = true;
+  }
+  return BO_OK;
+}
+
+bo_status check_acq(const bo_acq_params* a, AcqArgs* out) {
+  if (!a) return fail(BO_E_INVALID_ARG, "acq params are NULL");
+  if (a->mode != 0 && a->mode != 1) return fail(BO_E_INVALID_ARG, "acq mode %d is not 0 or 1", a->mode);
+  if (a->acq_bits & ~7u) return fail(BO_E_INVALID_ARG, "unknown acquisition bits 0x%x", a->acq_bits);
+  if (a->mode == 0 && !std::isfinite(a->lambda_const))
+    return fail(BO_E_INVALID_ARG, "lambda_const is not finite");
+  if (a->mode == 1 && !(a->mu_s > 0.0 && std::isfinite(a->mu_s)))
+    return fail(BO_E_INVALID_ARG, "contextual variance needs mu_s > 0");
+  if (a->mode == 1 && !std::isfinite(a->var_s_mean)) return fail(BO_E_INVALID_ARG, "var_s_mean is not finite");
+  out->mode = a->mode;
+  out->bits = a->acq_bits ? a->acq_bits : 7u;
+  out->lambda_const = a->lambda_const;
+  out->mu_s = a->mu_s;
+  out->var_s_mean = a->var_s_mean;
+  return BO_OK;
+}
+
+bo_status step_ready(bo_session* s) {
+  if (!s) return fail(BO_E_INVALID_ARG, "session is NULL");
+  if (!s->have_cand) return fail(BO_E_STATE, "no candidate set");
+  if (!s->have_fit) return fail(BO_E_STATE, "no fit");
+  return BO_OK;
+}
+
+bo_status enqueue_step(bo_session* s, const uint8_t* visited, const AcqArgs& a, bo_acq_result* out_dev) {
+  HIP_TRY(launch_posterior(s->P, s->lo, s->gp, s->n, s->n_valid, visited, a, s->stream));
+  HIP_TRY(launch_acquire(s->P, s->lo, s->n_valid, visited, a, out_dev, s->stream));
+  return BO_OK;
+}
+
+bo_status set_candidates(bo_session* s, const int32_t* levels, const int64_t* cand, const void* X, int x_is_f32,
+                         const uint8_t* invalid, int64_t* n_valid) {
+  if (!s) return fail(BO_E_INVALID_ARG, "session is NULL");
+  const int d = s->prob.d;
+  const int64_t N = s->prob.N;
+  if (!X) {
+    if (!levels) return fail(BO_E_INVALID_ARG, "levels is NULL");
+    __int128 total = 1;
+    for (int j = 0; j < d; ++j) {
+      if (levels[j] < 1) return fail(BO_E_INVALID_ARG, "levels[%d] = %d < 1", j, levels[j]);
+      total *= levels[j];
+      if (total > (__int128(1) << 62)) return fail(BO_E_INVALID_ARG, "grid too large");
+    }
+    if (!cand && (int64_t)total != N)
+      return fail(BO_E_INVALID_ARG, "grid size %lld != N %lld without a candidate list", (long long)total,
+                  (long long)N);
+  }
+  hipLaunchKernelGGL(k_state_clear, dim3(1), dim3(64), 0, s->stream, s->P.st, 0);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_grid_setup(s->P, s->lo, levels, d, cand, X, x_is_f32, invalid, N, s->stream));
+  bo_status rc = sync_state(s);
+  if (rc != BO_OK) return rc;
+  s->have_fit = 0;
+  if (s->hstate->post_status != BO_OK) {
+    s->have_cand = 0;
+    return fail(BO_E_INVALID_ARG, "candidate grid index out of range");
+  }
+  s->n_valid = s->hstate->n_unmasked;
+  s->have_cand = 1;
+  if (n_valid) *n_valid = s->n_valid;
+  return BO_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- layout --
+namespace bo {
+
+size_t bpk_bytes(int prec, int n_pad) {
+  if (prec == BO_BF16X3) {
+    const size_t JB = n_pad / 32;
+    return JB * (JB + 1) * 64 * 16 * 2;
+  }
+  const size_t JB = n_pad / 16;
+  return 2 * JB * (JB + 1) * 64 * (prec == BO_FP64 ? 8 : 4);
+}
+
+bool make_layout(const bo_problem& p, Layout* L) {
+  if (!problem_ok(&p)) return false;
+  Layout o{};
+  o.N = p.N;
+  o.N_pad = round_up(p.N, 256);
+  o.d = p.d;
+  o.n_max = p.n_max;
+  o.n_max_pad = n_pad_of(p.n_max);
+  o.prec = p.precision;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = (size_t)round_up((int64_t)(off + bytes), 256);
+    return at;
+  };
+  const size_t Np = (size_t)o.N_pad, np = (size_t)o.n_max_pad;
+  const size_t post_el = p.precision == BO_FP64 ? 8 : 4;
+  o.n_vslots = (int64_t)(Np / 16);
+  o.n_aslots = acquire_blocks(o.N_pad);
+  o.off_st = take(sizeof(DevState));
+  o.off_res = take(sizeof(bo_acq_result));
+  o.off_X64 = take((size_t)o.d * Np * 8);
+  o.off_X32 = take(p.precision == BO_BF16X3 ? (size_t)o.d * Np * 4 : 0);
+  o.off_orig = take(Np * 4);
+  o.off_inv = take((size_t)o.N * 4);
+  o.off_blk = take(((Np > (size_t)o.N ? Np : (size_t)o.N) / 1024 + 2) * 4);
+  o.off_mu = take(Np * post_el);
+  o.off_var = take(Np * post_el);
+  o.off_vslots = take((size_t)o.n_vslots * sizeof(VarSlot));
+  o.off_aslots = take((size_t)o.n_aslots * sizeof(AcqSlot));
+  o.off_Xo64 = take(np * kMaxD * 8);
+  o.off_Xo32 = take(np * kMaxD * 4);
+  o.off_y = take(np * 8);
+  o.off_A = take(np * np * 8);
+  o.off_L = take(np * np * 8);
+  o.off_Dinv = take((np / 32) * 32 * 32 * 8);
+  o.off_Linv = take(np * np * 8);
+  o.off_alpha = take(np * 8);
+  o.off_z = take(np * 8);
+  o.off_Bpk = take(bpk_bytes(p.precision, (int)np));
+  o.total = off;
+  *L = o;
+  return true;
+}
+
+DevPtrs carve(const Layout& o, uint8_t* b) {
+  DevPtrs P{};
+  P.st = (DevState*)(b + o.off_st);
+  P.res = (bo_acq_result*)(b + o.off_res);
+  P.X64 = (double*)(b + o.off_X64);
+  P.X32 = o.prec == BO_BF16X3 ? (float*)(b + o.off_X32) : nullptr;
+  P.orig = (int32_t*)(b + o.off_orig);
+  P.inv_map = (int32_t*)(b + o.off_inv);
+  P.blk = (int32_t*)(b + o.off_blk);
+  P.mu = b + o.off_mu;
+  P.var = b + o.off_var;
+  P.vslots = (VarSlot*)(b + o.off_vslots);
+  P.aslots = (AcqSlot*)(b + o.off_aslots);
+  P.Xo64 = (double*)(b + o.off_Xo64);
+  P.Xo32 = (float*)(b + o.off_Xo32);
+  P.y = (double*)(b + o.off_y);
+  P.A = (double*)(b + o.off_A);
+  P.L = (double*)(b + o.off_L);
+  P.Dinv = (double*)(b + o.off_Dinv);
+  P.Linv = (double*)(b + o.off_Linv);
+  P.alpha = (double*)(b + o.off_alpha);
+  P.z = (double*)(b + o.off_z);
+  P.Bpk = b + o.off_Bpk;
+  return P;
+}
+
+}  // namespace bo
+
+// ------------------------------------------------------------------ C ABI --
+extern "C" {
+
+const char* bo_version(void) { return "bo-mi355x 0.1 (gfx950)"; }
+
+const char* bo_last_error(void) { return g_err.c_str(); }
+
+bo_status bo_workspace_query(const bo_problem* prob, size_t* bytes) {
+  if (!bytes) return fail(BO_E_INVALID_ARG, "bytes is NULL");
+  Layout L;
+  if (!make_layout(*prob, &L))
+    return fail(BO_E_INVALID_ARG, "problem outside limits (1 <= N < 2^31, 1 <= d <= 16, 1 <= n_max <= 1024)");
+  *bytes = L.total;
+  return BO_OK;
+}
+
+bo_status bo_session_create(bo_session** out, const bo_problem* prob, const bo_gp_params* gp, void* workspace,
+                            size_t bytes, void* stream) {
+  if (!out) return fail(BO_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!problem_ok(prob)) return fail(BO_E_INVALID_ARG, "problem outside limits");
+  bo_gp_params g = {5, 7, 1.0, 1.0, 1e-6};
+  if (gp) g = *gp;
+  if (g.nu2 != 3 && g.nu2 != 5) return fail(BO_E_INVALID_ARG, "nu2 must be 3 or 5");
+  if (!(g.lengthscale > 0.0) || !std::isfinite(g.lengthscale)) return fail(BO_E_INVALID_ARG, "lengthscale");
+  if (!(g.amp > 0.0) || !std::isfinite(g.amp)) return fail(BO_E_INVALID_ARG, "amp");
+  if (!(g.noise >= 0.0) || !std::isfinite(g.noise)) return fail(BO_E_INVALID_ARG, "noise");
+  if (g.jitter_tries < 1 || g.jitter_tries > 20) return fail(BO_E_INVALID_ARG, "jitter_tries must be 1..20");
+  Layout L;
+  make_layout(*prob, &L);
+  if (!workspace || ((uintptr_t)workspace & 255u)) return fail(BO_E_WORKSPACE, "workspace NULL or not 256-aligned");
+  if (bytes < L.total)
+    return fail(BO_E_WORKSPACE, "workspace %zu bytes < %zu needed", bytes, L.total);
+  bo_session* s = new (std::nothrow) bo_session();
+  if (!s) return fail(BO_E_INVALID_ARG, "out of host memory");
+  s->prob = *prob;
+  s->gp = GpConst{g.nu2, g.jitter_tries, g.lengthscale, g.amp, g.noise};
+  s->lo = L;
+  s->ws = (uint8_t*)workspace;
+  s->ws_bytes = bytes;
+  s->P = carve(L, s->ws);
+  s->stream = (hipStream_t)stream;
+  hipError_t e = hipHostMalloc((void**)&s->hres, sizeof(bo_acq_result), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&s->hstate, sizeof(DevState), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    if (s->hres) (void)hipHostFree(s->hres);
+    delete s;
+    return fail(BO_E_HIP, "hipHostMalloc: %s", hipGetErrorString(e));
+  }
+  hipLaunchKernelGGL(k_state_clear, dim3(1), dim3(64), 0, s->stream, s->P.st, 1);
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    (void)hipHostFree(s->hres);
+    (void)hipHostFree(s->hstate);
+    delete s;
+    return fail(BO_E_HIP, "launch: %s", hipGetErrorString(e));
+  }
+  *out = s;
+  return BO_OK;
+}
+
+void bo_session_destroy(bo_session* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  (void)hipHostFree(s->hres);
+  (void)hipHostFree(s->hstate);
+  delete s;
+}
+
+bo_status bo_session_set_stream(bo_session* s, void* stream) {
+  if (!s) return fail(BO_E_INVALID_ARG, "session is NULL");
+  s->stream = (hipStream_t)stream;
+  return BO_OK;
+}
+
+bo_status bo_set_grid(bo_session* s, const int32_t* levels, const int64_t* cand, const uint8_t* invalid,
+                      int64_t* n_valid) {
+  return set_candidates(s, levels, cand, nullptr, 0, invalid, n_valid);
+}
+
+bo_status bo_set_candidates(bo_session* s, const void* X, int32_t x_is_f32, const uint8_t* invalid,
+                            int64_t* n_valid) {
+  if (!X) return fail(BO_E_INVALID_ARG, "X is NULL");
+  if (x_is_f32 != 0 && x_is_f32 != 1) return fail(BO_E_INVALID_ARG, "x_is_f32 must be 0 or 1");
+  return set_candidates(s, nullptr, nullptr, X, x_is_f32, invalid, n_valid);
+}
+
+bo_status bo_gp_fit(bo_session* s, const int64_t* obs_idx, const double* y, int32_t n) {
+  if (!s) return fail(BO_E_INVALID_ARG, "session is NULL");
+  if (!s->have_cand) return fail(BO_E_STATE, "no candidate set");
+  if (n < 1) return fail(BO_E_STATE, "a fit needs at least one observation (n = %d)", n);
+  if (n > s->prob.n_max) return fail(BO_E_INVALID_ARG, "n = %d exceeds n_max = %d", n, s->prob.n_max);
+  if (!obs_idx || !y) return fail(BO_E_INVALID_ARG, "obs_idx or y is NULL");
+  s->n = n;
+  s->fit_attempt = 0;
+  if (n <= kSmallFitMax)
+    HIP_TRY(launch_fit_small(s->P, s->lo, s->gp, obs_idx, y, n, s->stream));
+  else
+    HIP_TRY(launch_fit_large(s->P, s->lo, s->gp, obs_idx, y, n, 0, s->stream));
+  s->have_fit = 1;
+  return BO_OK;
+}
+
+bo_status bo_fit_read(bo_session* s, bo_fit_info* info, double* alpha, double* Linv) {
+  if (!s) return fail(BO_E_INVALID_ARG, "session is NULL");
+  if (!s->have_fit) return fail(BO_E_STATE, "no fit");
+  bool retried;
+  bo_status rc = settle_fit(s, &retried);
+  if (rc != BO_OK) return rc;
+  const DevState& h = *s->hstate;
+  if (info) {
+    info->status = h.status;
+    info->n = h.n;
+    info->attempt = h.attempt;
+    info->reserved = 0;
+    info->jitter = h.jitter;
+    info->mean_y = h.mean_y;
+    info->f_best = h.f_best;
+  }
+  const int n = s->n, np = n_pad_of(n);
+  if (alpha) HIP_TRY(hipMemcpy(alpha, s->P.alpha, sizeof(double) * n, hipMemcpyDeviceToHost));
+  if (Linv)
+    HIP_TRY(hipMemcpy2D(Linv, sizeof(double) * n, s->P.Linv, sizeof(double) * np, sizeof(double) * n, n,
+                        hipMemcpyDeviceToHost));
+  if (h.status != BO_OK) return fail((bo_status)h.status, "fit failed with status %d", h.status);
+  return BO_OK;
+}
+
+bo_status bo_posterior(bo_session* s, const uint8_t* visited, double* mu, double* var, double* var_mean) {
+  bo_status rc = step_ready(s);
+  if (rc != BO_OK) return rc;
+  if (s->n_valid == 0) return fail(BO_E_NO_CANDIDATE, "every candidate is invalid");
+  AcqArgs a{0, 7u, 0.0, 0.0, 0.0};
+  for (int round = 0; round < 2; ++round) {
+    HIP_TRY(launch_posterior(s->P, s->lo, s->gp, s->n, s->n_valid, visited, a, s->stream));
+    if (mu || var) HIP_TRY(launch_scatter_posterior(s->P, s->lo, s->n_valid, visited, mu, var, s->stream));
+    if (!var_mean) return BO_OK;
+    bool retried;
+    rc = settle_fit(s, &retried);
+    if (rc != BO_OK) return rc;
+    if (!retried) break;
+  }
+  const DevState& h = *s->hstate;
+  if (h.status != BO_OK) return fail((bo_status)h.status, "fit failed with status %d", h.status);
+  *var_mean = h.var_mean;
+  if (h.post_status != BO_OK) return fail((bo_status)h.post_status, "posterior status %d", h.post_status);
+  return BO_OK;
+}
+
+bo_status bo_acquire(bo_session* s, const uint8_t* visited, const bo_acq_params* params, bo_acq_result* out) {
+  bo_status rc = step_ready(s);
+  if (rc != BO_OK) return rc;
+  if (!out) return fail(BO_E_INVALID_ARG, "out is NULL");
+  AcqArgs a;
+  rc = check_acq(params, &a);
+  if (rc != BO_OK) return rc;
+  if (s->n_valid == 0) {
+    bo_acq_result r{};
+    for (int k = 0; k < 3; ++k) {
+      r.idx[k] = -1;
+      r.score[k] = NAN;
+    }
+    r.status = BO_E_NO_CANDIDATE;
+    *out = r;
+    return fail(BO_E_NO_CANDIDATE, "every candidate is invalid");
+  }
+  for (int round = 0; round < 2; ++round) {
+    rc = enqueue_step(s, visited, a, s->P.res);
+    if (rc != BO_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(s->hres, s->P.res, sizeof(bo_acq_result), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (!(s->hres->status == BO_E_NOT_PD && s->n > kSmallFitMax)) break;
+    bool retried;
+    rc = settle_fit(s, &retried);
+    if (rc != BO_OK) return rc;
+    if (!retried) break;
+  }
+  *out = *s->hres;
+  if (out->status != BO_OK) return fail((bo_status)out->status, "step finished with status %d", out->status);
+  return BO_OK;
+}
+
+bo_status bo_acquire_async(bo_session* s, const uint8_t* visited, const bo_acq_params* params,
+                           bo_acq_result* out_dev) {
+  bo_status rc = step_ready(s);
+  if (rc != BO_OK) return rc;
+  if (!out_dev) return fail(BO_E_INVALID_ARG, "out_dev is NULL");
+  AcqArgs a;
+  rc = check_acq(params, &a);
+  if (rc != BO_OK) return rc;
+  if (s->n_valid == 0) return fail(BO_E_NO_CANDIDATE, "every candidate is invalid");
+  return enqueue_step(s, visited, a, out_dev);
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+"""BF16X3 precision mode against the FP64 oracle.
+
+The cross-covariance and L^-1 enter the matrix cores as bfloat16 high and low
+parts (16 significant bits each value) and three products are accumulated in
+FP32, so each contraction term carries a relative error of about 2^-16 and the
+posterior variance an absolute error of a few 1e-5.  The tolerance TOL_B =
+2e-4 (normwise, same scale floors as the FP64/FP32 modes) is derived from that
+arithmetic; the measured errors are printed as the mode's error report.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2111_14991_amd import workloads as W
+from tests import parity as PR
+
+pytestmark = pytest.mark.gpu
+
+TOL_B = 2e-4
+
+
+@pytest.fixture(scope="module")
+def bo():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_2111_14991_amd as bo
+    bo.lib()
+    return bo
+
+
+def _report(name, err):
+    q = np.quantile(err, [0.5, 0.99, 1.0]) if err.size else np.zeros(3)
+    print(f"{name}: median {q[0]:.2e} p99 {q[1]:.2e} max {q[2]:.2e}")
+    return q[2]
+
+
+@pytest.mark.parametrize("n", [1, 37, 100, 300, 1000])
+def test_bf16x3_mid_size_parity(bo, n):
+    s = W.make_session(20 + n, (6, 6, 6, 6, 6), n, invalid_frac=0.3)
+    S = bo.Session(s.N, s.d, s.n, "bf16x3")
+    S.set_grid(s.levels, None, s.invalid)
+    S.fit(s.obs_idx, s.y)
+    mu_s = float(np.mean(s.y[:s.n_init]))
+    r = S.acquire(s.visited(), bo.AcqParams(mode=1, mu_s=mu_s))
+    mu, var, vm = S.posterior(s.visited())
+    mu, var = mu.cpu().numpy(), var.cpu().numpy()
+    X = oracle.normalize_grid(s.levels)
+    ref = oracle.step(X, s.invalid, s.visited(), s.obs_idx, s.y, acq=oracle.Acq(mode=1, mu_s=mu_s),
+                      want_posterior=True)
+    mask = (s.invalid | s.visited()).astype(bool)
+    keep = ~mask
+    np.testing.assert_array_equal(np.isnan(mu), mask)
+    ymax = np.abs(s.y).max()
+    e_mu = _report(f"n={n} mu", np.abs(mu[keep] - ref.mu[keep]) / np.maximum(np.abs(ref.mu[keep]), ymax))
+    e_var = _report(f"n={n} var", np.abs(var[keep] - ref.var[keep]))
+    assert e_mu <= TOL_B and e_var <= TOL_B
+    # the mean variance carries the variance's absolute error (floor amp = 1)
+    assert abs(r.var_mean - ref.var_mean) <= TOL_B * max(ref.var_mean, 1.0)
+    assert abs(r.lam - ref.lam) <= TOL_B * ref.lam
+    A_r = PR.acq_arrays(ref.mu, ref.var, ref.f_best, ref.lam, mask)
+    A_g = PR.acq_arrays(mu, var, r.f_best, r.lam, mask)
+    scales = (1.0, 1.0, ymax)
+    for q, name in enumerate(("ei", "pi", "lcb")):
+        e = np.abs(A_g[keep, q] - A_r[keep, q]) / np.maximum(np.abs(A_r[keep, q]), scales[q])
+        _report(f"n={n} {name}", e)
+        assert PR.index_ok(int(r.idx[q]), int(ref.idx[q]), A_r, q, mask, TOL_B, scales[q]), (q, r.idx, ref.idx)
+    S.close()
+
+
+def test_bf16x3_full_size_sampled(bo):
+    """1,048,576 candidates, n = 1000, in the launch configuration the
+    benchmark times; the oracle checks 1,500 sampled candidates one by one, the
+    chosen indices, and the best 64 candidates of each acquisition."""
+    s = W.config_c3(0)
+    S = bo.Session(s.N, s.d, s.n, "bf16x3")
+    S.set_grid(s.levels, None, s.invalid)
+    vis = s.visited()
+    mu_s = float(np.mean(s.y[:s.n_init]))
+    S.fit(s.obs_idx, s.y)
+    r = S.acquire(vis, bo.AcqParams(mode=1, mu_s=mu_s))
+    assert r.status == 0
+    mu, var, vm = S.posterior(vis)
+    mu, var = mu.cpu().numpy(), var.cpu().numpy()
+    mask = (s.invalid | vis).astype(bool)
+    assert r.n_unmasked == int((~mask).sum())
+    assert np.array_equal(np.isnan(mu), mask)
+    # mean variance consistent with the variances the GPU returned
+    assert abs(vm - np.mean(var[~mask], dtype=np.float64)) <= 1e-6 * vm
+    Xo = oracle.normalize_grid(s.levels, s.obs_idx)
+    f = oracle.fit(Xo, s.y)
+    rng = np.random.Generator(np.random.PCG64(7))
+    samp = rng.choice(np.flatnonzero(~mask), 1500, replace=False)
+    m_r, v_r = oracle.predict(f, oracle.normalize_grid(s.levels, samp))
+    ymax = np.abs(s.y).max()
+    e_mu = _report("c3 mu", np.abs(mu[samp] - m_r) / np.maximum(np.abs(m_r), ymax))
+    e_var = _report("c3 var", np.abs(var[samp] - v_r))
+    assert e_mu <= TOL_B and e_var <= TOL_B
+    # lambda from the first-step formula with the GPU mean variance
+    assert abs(r.lam - r.f_best / mu_s) <= 1e-12 * r.lam
+    # chosen indices: the oracle's value at each chosen index is within
+    # tolerance of the oracle's best over the 64 best GPU candidates
+    keep = np.flatnonzero(~mask)
+    tau = r.f_best - r.lam
+    sg = np.sqrt(var[keep])
+    from scipy.special import erfc
+    z = (tau - mu[keep]) / np.where(sg > 0, sg, 1.0)
+    Phi = 0.5 * erfc(-z / np.sqrt(2))
+    ei = (tau - mu[keep]) * Phi + sg * np.exp(-0.5 * z * z) / np.sqrt(2 * np.pi)
+    lcb = mu[keep] - r.lam * sg
+    scales = (1.0, 1.0, ymax)
+    for q, score in enumerate((ei, Phi, -lcb)):
+        top = keep[np.argsort(-score, kind="stable")[:64]]
+        cand = np.unique(np.concatenate([top, [r.idx[q]]]))
+        m_t, v_t = oracle.predict(f, oracle.normalize_grid(s.levels, cand))
+        a_t = np.array([oracle.acquisitions(m, v, r.f_best, r.lam)[q] for m, v in zip(m_t, v_t)])
+        a_t = a_t if q < 2 else -a_t
+        mine = a_t[np.flatnonzero(cand == r.idx[q])[0]]
+        assert mine >= a_t.max() - TOL_B * max(abs(a_t.max()), scales[q]), (q, mine, a_t.max())
+        got = r.score[q] if q < 2 else -r.score[q]
+        assert abs(got - mine) <= TOL_B * max(abs(mine), scales[q])
+    S.close()
