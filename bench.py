@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the Gaussian-process surrogate BO step on one MI355X.
+
+One step = refit on the session's observations (FP64 Cholesky, jitter,
+alpha, L^-1) + posterior over every valid candidate + EI/PI/LCB with the
+contextual-variance exploration factor + masked arg-optimum, result on the
+host.  Inputs are seeded synthetic landscapes resident in HBM before timing.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|c1]
+
+Prints one JSON line: throughput in candidate posterior+acquisition evals/s
+(unmasked candidates per step / step time), step latency percentiles, phase
+times, the roofline of the posterior kernel, and the FP64 CPU oracle timed
+on this host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}  # dense TFLOP/s, MI355X
+HBM_GBS = 8000.0
+
+WORKLOADS = {
+    "c3": dict(fn="config_c3", precision="bf16x3", dtype="bf16", peak="bf16",
+               desc="1,048,576-point 4^10 grid, 30% invalid, n=1000 observations, BF16X3 posterior"),
+    "c2": dict(fn="config_c2", precision="fp32", dtype="fp32", peak="fp32",
+               desc="102,060-point 8-parameter grid, 25% invalid, n=220 observations, FP32 posterior"),
+    "c1": dict(fn="config_c1", precision="fp64", dtype="fp64", peak="fp64",
+               desc="1,536-point 8x8x6x4 grid, 144 invalid, n=20 observations, FP64 posterior"),
+}
+POSTERIOR_KERNEL = {"bf16x3": "k_post_bf16x3", "fp32": "k_post16", "fp64": "k_post16"}
+KERNEL_SOURCE = {"bf16x3": "paper_2111_14991_amd/csrc/k_bf16x3.hip", "fp32": "paper_2111_14991_amd/csrc/k_posterior.hip",
+                 "fp64": "paper_2111_14991_amd/csrc/k_posterior.hip"}
+
+
+def source_hash(rel: str) -> str:
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profile(precision: str, workload: str):
+    """HBM bytes per launch of the posterior kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{POSTERIOR_KERNEL[precision]}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256_16") != source_hash(KERNEL_SOURCE[precision]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(s, n_unmasked: int, budget_s: float = 12.0):
+    """FP64 oracle on this host: the fit on all observations plus the
+    posterior of a sample of unmasked candidates, extrapolated linearly to the
+    whole step (acquisition and arg-optimum are negligible next to it)."""
+    import oracle
+    Xo = oracle.normalize_grid(s.levels, s.grid_index(s.obs_idx))
+    t0 = time.perf_counter()
+    f = oracle.fit(Xo, s.y)
+    t_fit = time.perf_counter() - t0
+    mask = (s.invalid | s.visited()).astype(bool)
+    pool = np.flatnonzero(~mask)
+    rng = np.random.Generator(np.random.PCG64(11))
+    probe = rng.choice(pool, min(pool.size, 256), replace=False)
+    P = oracle.normalize_grid(s.levels, s.grid_index(probe))
+    t0 = time.perf_counter()
+    oracle.predict(f, P)
+    t_probe = time.perf_counter() - t0
+    per = t_probe / probe.size
+    m = int(min(pool.size, max(probe.size, budget_s / max(per, 1e-9))))
+    samp = rng.choice(pool, m, replace=False)
+    P = oracle.normalize_grid(s.levels, s.grid_index(samp))
+    t0 = time.perf_counter()
+    oracle.predict(f, P)
+    t_pred = time.perf_counter() - t0
+    t_step = t_fit + t_pred * n_unmasked / m
+    return {"value": n_unmasked / t_step, "unit": "candidate-evals/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle fit on all {s.n} observations ({t_fit:.3f} s) + posterior of {m} of "
+                      f"{n_unmasked} unmasked candidates ({t_pred:.2f} s), extrapolated linearly to the step",
+            "step_s_estimate": t_step}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the BO step runs on a single MI355X); --gpus {args.gpus} "
+              "is not supported", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2111_14991_amd as bo
+    from paper_2111_14991_amd import workloads as W
+
+    wl = WORKLOADS[args.workload]
+    s = getattr(W, wl["fn"])(0)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    S = bo.Session(s.N, s.d, s.n, wl["precision"], device=dev)
+    n_valid = S.set_grid(s.levels, s.cand, s.invalid)
+    obs = torch.as_tensor(s.obs_idx).to(dev)
+    y = torch.as_tensor(s.y).to(dev)
+    vis = torch.as_tensor(s.visited()).to(dev)
+    n_unmasked = int(n_valid - s.n)
+
+    # contextual-variance constants from the initial sample (Section III-F)
+    n0 = s.n_init
+    vis0 = torch.zeros_like(vis)
+    vis0[obs[:n0]] = 1
+    S.fit(obs[:n0].contiguous(), y[:n0].contiguous())
+    var_s = S.acquire(vis0, bo.AcqParams(mode=0)).var_mean
+    acq = bo.AcqParams(mode=1, mu_s=float(np.mean(s.y[:n0])), var_s_mean=var_s)
+
+    S.set_timing(True)
+    for _ in range(args.warmup):
+        S.fit(obs, y)
+        r = S.acquire(vis, acq)
+    torch.cuda.synchronize()
+    lat, phases = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        S.fit(obs, y)
+        r = S.acquire(vis, acq)
+        lat.append(time.perf_counter() - ts)
+        phases.append(S.timing())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert r.status == 0 and r.n_unmasked == n_unmasked, (r.status, r.n_unmasked, n_unmasked)
+
+    ms_per_step = (t1 - t0) / args.steps * 1e3
+    ph = np.array(phases)
+    post_ms = float(ph[:, 1].mean())
+    n, d = s.n, s.d
+    # algorithmic work of one posterior launch: every valid candidate against
+    # every observation -- triangular solve n^2, distance+Matern (3d+12)n, mean 2n
+    flops = float(n_valid) * (n * n + (3 * d + 12) * n + 2 * n)
+    achieved = flops / (post_ms * 1e-3) / 1e12
+    peak = PEAK[wl["peak"]]
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": traffic_from_profile(wl["precision"], args.workload),
+                "kernel": POSTERIOR_KERNEL[wl["precision"]], "kernel_ms": post_ms}
+    if wl["precision"] == "bf16x3":
+        # the three bfloat16 products issued per algorithmic multiply-add
+        mfma = float(n_valid) * 3 * n * (n + 1)
+        roofline["mfma_issued_tflops"] = mfma / (post_ms * 1e-3) / 1e12
+        roofline["mfma_issued_frac"] = roofline["mfma_issued_tflops"] / peak
+
+    line = {
+        "metric": "candidate posterior+acquisition evals/s; BO step p50/p99 latency",
+        "value": n_unmasked / (ms_per_step * 1e-3),
+        "unit": "candidate-evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": wl["dtype"], "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {wl['desc']}", "candidates": int(s.N), "valid": int(n_valid),
+                   "unmasked": n_unmasked, "observations": int(n), "dims": int(d), "precision": wl["precision"]},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
+                       "mean": float(np.mean(lat) * 1e3)},
+        "phases_ms": {"fit": float(ph[:, 0].mean()), "posterior": post_ms, "acquire": float(ph[:, 2].mean())},
+        "roofline": roofline,
+        "cpu_baseline": None if args.no_cpu else cpu_baseline(s, n_unmasked),
+        "chosen": [int(v) for v in r.idx],
+    }
+    print(json.dumps(line), flush=True)
+    S.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

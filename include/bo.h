@@ -200,6 +200,16 @@ bo_status bo_acquire(bo_session* s, const uint8_t* visited, const bo_acq_params*
 bo_status bo_acquire_async(bo_session* s, const uint8_t* visited, const bo_acq_params* params,
                            bo_acq_result* out_dev);
 
+/* Phase timing.  With timing enabled the library records HIP events on the
+ * session stream around its own launches: the fit (bo_gp_fit), the posterior
+ * kernel and the acquisition kernel (bo_posterior / bo_acquire).
+ * bo_get_timing is synchronizing and returns the durations, in milliseconds,
+ * of the most recent fit, posterior and acquisition (-1 for a phase that has
+ * not run since timing was enabled).  The events are created by
+ * bo_set_timing, never on the step path. */
+bo_status bo_set_timing(bo_session* s, int32_t enable);
+bo_status bo_get_timing(bo_session* s, float* fit_ms, float* posterior_ms, float* acquire_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,8 @@ _SIGS = {
     "bo_posterior": (C.c_int, [_VP, _U8P, _DP, _DP, C.POINTER(C.c_double)]),
     "bo_acquire": (C.c_int, [_VP, _U8P, C.POINTER(bo_acq_params), C.POINTER(bo_acq_result)]),
     "bo_acquire_async": (C.c_int, [_VP, _U8P, C.POINTER(bo_acq_params), _VP]),
+    "bo_set_timing": (C.c_int, [_VP, C.c_int32]),
+    "bo_get_timing": (C.c_int, [_VP, C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float)]),
 }
 
 
@@ -293,6 +295,19 @@ class Session:
         if check and rc not in (BO_OK,):
             raise BOError(rc, "bo_acquire", last_error())
         return _result(r)
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().bo_set_timing(self.h, 1 if enable else 0), "bo_set_timing")
+
+    def timing(self):
+        """(fit, posterior, acquire) durations in ms of the latest phases."""
+        f, p, a = C.c_float(), C.c_float(), C.c_float()
+        _check(lib().bo_get_timing(self.h, C.byref(f), C.byref(p), C.byref(a)), "bo_get_timing")
+        return f.value, p.value, a.value
+
+    def posterior_async(self, visited=None):
+        """Enqueue only the posterior (no outputs, no synchronization)."""
+        _check(lib().bo_posterior(self.h, _ptr(visited), None, None, None), "bo_posterior")
 
     def acquire_async(self, out_dev, visited=None, acq: Optional[AcqParams] = None):
         """Enqueue a step writing its result record into `out_dev` (a device

@@ -32,6 +32,9 @@ struct bo_session {
   int fit_attempt;
   bo_acq_result* hres;  // pinned host copy of the device result
   DevState* hstate;     // pinned host copy of the device state
+  int timing;
+  hipEvent_t ev[6];     // fit begin/end, posterior begin/end, acquire begin/end
+  int ev_have[3];
 };
 
 namespace {
@@ -117,9 +120,33 @@ bo_status step_ready(bo_session* s) {
   return BO_OK;
 }
 
-bo_status enqueue_step(bo_session* s, const uint8_t* visited, const AcqArgs& a, bo_acq_result* out_dev) {
+bo_status mark(bo_session* s, int which) {
+  if (s->timing) {
+    HIP_TRY(hipEventRecord(s->ev[which], s->stream));
+    if (which & 1) s->ev_have[which >> 1] = 1;
+  }
+  return BO_OK;
+}
+
+#define MARK(s, w)                   \
+  do {                               \
+    bo_status m_ = mark((s), (w));   \
+    if (m_ != BO_OK) return m_;      \
+  } while (0)
+
+bo_status enqueue_posterior(bo_session* s, const uint8_t* visited, const AcqArgs& a) {
+  MARK(s, 2);
   HIP_TRY(launch_posterior(s->P, s->lo, s->gp, s->n, s->n_valid, visited, a, s->stream));
+  MARK(s, 3);
+  return BO_OK;
+}
+
+bo_status enqueue_step(bo_session* s, const uint8_t* visited, const AcqArgs& a, bo_acq_result* out_dev) {
+  bo_status rc = enqueue_posterior(s, visited, a);
+  if (rc != BO_OK) return rc;
+  MARK(s, 4);
   HIP_TRY(launch_acquire(s->P, s->lo, s->n_valid, visited, a, out_dev, s->stream));
+  MARK(s, 5);
   return BO_OK;
 }
 
@@ -307,6 +334,8 @@ bo_status bo_session_create(bo_session** out, const bo_problem* prob, const bo_g
 void bo_session_destroy(bo_session* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->stream);
+  if (s->timing)
+    for (int i = 0; i < 6; ++i) (void)hipEventDestroy(s->ev[i]);
   (void)hipHostFree(s->hres);
   (void)hipHostFree(s->hstate);
   delete s;
@@ -338,10 +367,12 @@ bo_status bo_gp_fit(bo_session* s, const int64_t* obs_idx, const double* y, int3
   if (!obs_idx || !y) return fail(BO_E_INVALID_ARG, "obs_idx or y is NULL");
   s->n = n;
   s->fit_attempt = 0;
+  MARK(s, 0);
   if (n <= kSmallFitMax)
     HIP_TRY(launch_fit_small(s->P, s->lo, s->gp, obs_idx, y, n, s->stream));
   else
     HIP_TRY(launch_fit_large(s->P, s->lo, s->gp, obs_idx, y, n, 0, s->stream));
+  MARK(s, 1);
   s->have_fit = 1;
   return BO_OK;
 }
@@ -377,7 +408,8 @@ bo_status bo_posterior(bo_session* s, const uint8_t* visited, double* mu, double
   if (s->n_valid == 0) return fail(BO_E_NO_CANDIDATE, "every candidate is invalid");
   AcqArgs a{0, 7u, 0.0, 0.0, 0.0};
   for (int round = 0; round < 2; ++round) {
-    HIP_TRY(launch_posterior(s->P, s->lo, s->gp, s->n, s->n_valid, visited, a, s->stream));
+    rc = enqueue_posterior(s, visited, a);
+    if (rc != BO_OK) return rc;
     if (mu || var) HIP_TRY(launch_scatter_posterior(s->P, s->lo, s->n_valid, visited, mu, var, s->stream));
     if (!var_mean) return BO_OK;
     bool retried;
@@ -435,6 +467,33 @@ bo_status bo_acquire_async(bo_session* s, const uint8_t* visited, const bo_acq_p
   if (rc != BO_OK) return rc;
   if (s->n_valid == 0) return fail(BO_E_NO_CANDIDATE, "every candidate is invalid");
   return enqueue_step(s, visited, a, out_dev);
+}
+
+bo_status bo_set_timing(bo_session* s, int32_t enable) {
+  if (!s) return fail(BO_E_INVALID_ARG, "session is NULL");
+  if (enable && !s->timing) {
+    for (int i = 0; i < 6; ++i) HIP_TRY(hipEventCreate(&s->ev[i]));
+    s->ev_have[0] = s->ev_have[1] = s->ev_have[2] = 0;
+    s->timing = 1;
+  } else if (!enable && s->timing) {
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int i = 0; i < 6; ++i) HIP_TRY(hipEventDestroy(s->ev[i]));
+    s->timing = 0;
+  }
+  return BO_OK;
+}
+
+bo_status bo_get_timing(bo_session* s, float* fit_ms, float* posterior_ms, float* acquire_ms) {
+  if (!s) return fail(BO_E_INVALID_ARG, "session is NULL");
+  if (!s->timing) return fail(BO_E_STATE, "timing is not enabled");
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  float* outs[3] = {fit_ms, posterior_ms, acquire_ms};
+  for (int k = 0; k < 3; ++k) {
+    if (!outs[k]) continue;
+    *outs[k] = -1.f;
+    if (s->ev_have[k]) HIP_TRY(hipEventElapsedTime(outs[k], s->ev[2 * k], s->ev[2 * k + 1]));
+  }
+  return BO_OK;
 }
 
 }  // extern "C"
