@@ -232,7 +232,7 @@ bool make_layout(const bo_problem& p, Layout* L) {
   o.off_y = take(np * 8);
   o.off_A = take(np * np * 8);
   o.off_L = take(np * np * 8);
-  o.off_Dinv = take((np / 32) * 32 * 32 * 8);
+  o.off_Dinv = take((np / 64) * 64 * 64 * 8);
   o.off_Linv = take(np * np * 8);
   o.off_alpha = take(np * 8);
   o.off_z = take(np * 8);
@@ -395,9 +395,13 @@ bo_status bo_fit_read(bo_session* s, bo_fit_info* info, double* alpha, double* L
   }
   const int n = s->n, np = n_pad_of(n);
   if (alpha) HIP_TRY(hipMemcpy(alpha, s->P.alpha, sizeof(double) * n, hipMemcpyDeviceToHost));
-  if (Linv)
+  if (Linv) {
     HIP_TRY(hipMemcpy2D(Linv, sizeof(double) * n, s->P.Linv, sizeof(double) * np, sizeof(double) * n, n,
                         hipMemcpyDeviceToHost));
+    // only the lower triangle of L^-1 is kept on the device
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) Linv[(size_t)i * n + j] = 0.0;
+  }
   if (h.status != BO_OK) return fail((bo_status)h.status, "fit failed with status %d", h.status);
   return BO_OK;
 }
