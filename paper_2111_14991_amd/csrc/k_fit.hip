@@ -39,6 +39,7 @@ struct FitArgs {
   double* L;
   double* Dinv;  // inverses of the diagonal tiles of L
   double* Linv;  // X = L^-1
+  double* K0;    // symmetric copy of amp * Matern without jitter, or null
   double* alpha;
   double* z;
   void* Bpk;
@@ -150,18 +151,23 @@ __device__ void op_build(const FitArgs& a, int ti, int tj, double delta, double*
     const int r = 16 * w + i;
     const int gi = ti * T + r;
     const double* xr = xs + r * (kMaxD + 1);
-    double v;
+    double v, v0 = 0.0;
     if (gi < a.n && gj < a.n) {
       double s2 = 0.0;
       for (int k = 0; k < a.d; ++k) {
         const double df = xr[k] - xc[k];
         s2 += df * df;
       }
-      v = a.amp * matern64(a.nu2, sqrt(s2), a.inv_l) + (gi == gj ? delta : 0.0);
+      v0 = a.amp * matern64(a.nu2, sqrt(s2), a.inv_l);
+      v = v0 + (gi == gj ? delta : 0.0);
     } else {
       v = gi == gj ? 1.0 : 0.0;
     }
     a.A[tix(a, ti, tj, r, c)] = v;
+    if (a.K0) {
+      a.K0[(size_t)gi * a.n_pad + gj] = v0;
+      a.K0[(size_t)gj * a.n_pad + gi] = v0;
+    }
   }
   __syncthreads();
 }
@@ -602,6 +608,7 @@ FitArgs make_args(const DevPtrs& P, const Layout& Lo, const GpConst& g, const in
   a.L = P.L;
   a.Dinv = P.Dinv;
   a.Linv = P.Linv;
+  a.K0 = P.K0;
   a.alpha = P.alpha;
   a.z = P.z;
   a.Bpk = P.Bpk;

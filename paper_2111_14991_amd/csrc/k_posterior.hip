@@ -2,16 +2,28 @@
 //
 // Each wave owns 16 compacted candidates.  For them it generates the FP64
 // cross-covariance k* = amp Matern(|x_c - x_i|) against every observation,
-// accumulates the mean mu = m + k*^T alpha in FP64, and parks k* (FP64, or
-// rounded to FP32) in LDS in the A-operand order of a 16x16x4 matrix-core
-// product.  The variance contraction W = K* L^-T runs on the matrix cores
-// against the packed lower-triangular L^-1, column block by column block,
-// skipping the all-zero tiles above the diagonal; FP32 products are summed in
-// chunks of 16 observations and the chunks are added in FP64.  Then
-// var = amp - sum_j W_cj^2, clamped at zero.  A workgroup publishes the sum and
-// count of variances over its not-yet-evaluated candidates; the last
-// workgroup reduces them in slot order to the mean variance and the
-// exploration factor of Section III-F.
+// accumulates the mean mu = m + k*^T alpha in FP64, and parks the operand of
+// the variance contraction in LDS in the A-operand order of a 16x16x4
+// matrix-core product.  The contraction W = (operand) L^-T runs on the matrix
+// cores against the packed lower-triangular L^-1, column block by column
+// block, skipping the all-zero tiles above the diagonal.
+//
+// FP64 mode: the operand is k* and var = amp - |W|^2.
+//
+// FP32 mode (compensated): products are summed on FP32 matrix cores in chunks
+// of 16 observations and the chunks are added in FP64.  Rounding k* and L^-1
+// to FP32 would leave errors proportional to |k*| |L^-1|, which is large next
+// to the variance near the data.  Instead the operand is the residual
+// r = k* - K e_p against the nearest observation p (K = K_nn with the accepted
+// jitter delta).  Because L^-1 K e_p = L^T e_p exactly,
+//     k*^T K^-1 k* = K_pp + 2 r_p + |L^-1 r|^2,
+// hence var = 2 (amp - k*_p) + delta - |L^-1 r|^2, whose first two terms are
+// exact in FP64 and whose rounded part shrinks with the distance to the data
+// (the identity holds for any p; the nearest one minimizes |r|).
+//
+// A workgroup publishes the sum and count of variances over its
+// not-yet-evaluated candidates; the last workgroup reduces them in slot order
+// to the mean variance and the exploration factor of Section III-F.
 #include "bo_internal.h"
 #include "bo_device.h"
 #include "post_common.h"
@@ -42,23 +54,85 @@ __global__ __launch_bounds__(256) void k_post16(PostArgs p) {
 #pragma unroll
   for (int j = 0; j < kMaxD; ++j) xr[j] = j < p.d ? p.X64[(int64_t)j * p.N_pad + my_row] : 0.0;
   double mu_part = 0.0;
-  for (int t = 0; t < nt4; ++t) {
-    const int i = 4 * t + my_k;
-    double kv = 0.0;
-    if (i < p.n) {
-      const double* xo = p.Xo64 + (size_t)i * kMaxD;
-      double s = 0.0;
+  double base = 0.0;  // FP32 mode: 2 (amp - k*_p) + delta, on every lane of the row
+  if constexpr (!F32) {
+    for (int t = 0; t < nt4; ++t) {
+      const int i = 4 * t + my_k;
+      double kv = 0.0;
+      if (i < p.n) {
+        const double* xo = p.Xo64 + (size_t)i * kMaxD;
+        double s = 0.0;
 #pragma unroll
-      for (int j = 0; j < kMaxD; ++j) {
-        if (j < p.d) {
-          const double df = xr[j] - xo[j];
-          s += df * df;
+        for (int j = 0; j < kMaxD; ++j) {
+          if (j < p.d) {
+            const double df = xr[j] - xo[j];
+            s += df * df;
+          }
+        }
+        kv = p.amp * matern64(p.nu2, sqrt(s), p.inv_l);
+        mu_part += kv * p.alpha[i];
+      }
+      kt[t * 64 + l] = (KT)kv;
+    }
+  } else {
+    // nearest observation of the row: the four lanes of a row scan disjoint
+    // observations, then compare (distance, index) pairs
+    double best = __builtin_inf();
+    int bi = 0;
+    for (int t = 0; t < nt4; ++t) {
+      const int i = 4 * t + my_k;
+      if (i < p.n) {
+        const double* xo = p.Xo64 + (size_t)i * kMaxD;
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < kMaxD; ++j) {
+          if (j < p.d) {
+            const double df = xr[j] - xo[j];
+            s += df * df;
+          }
+        }
+        if (s < best) {
+          best = s;
+          bi = i;
         }
       }
-      kv = p.amp * matern64(p.nu2, sqrt(s), p.inv_l);
-      mu_part += kv * p.alpha[i];
     }
-    kt[t * 64 + l] = (KT)kv;
+#pragma unroll
+    for (int m = 16; m <= 32; m <<= 1) {
+      const double ob = shfl_xor_d(best, m);
+      const int oi = __shfl_xor(bi, m, 64);
+      if (ob < best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    const double jit = p.st->jitter;
+    const double* krow = p.K0 + (size_t)bi * p.n_pad;
+    for (int t = 0; t < nt4; ++t) {
+      const int i = 4 * t + my_k;
+      double rv = 0.0;
+      if (i < p.n) {
+        const double* xo = p.Xo64 + (size_t)i * kMaxD;
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < kMaxD; ++j) {
+          if (j < p.d) {
+            const double df = xr[j] - xo[j];
+            s += df * df;
+          }
+        }
+        const double kv = p.amp * matern64(p.nu2, sqrt(s), p.inv_l);
+        mu_part += kv * p.alpha[i];
+        rv = kv - krow[i];
+        if (i == bi) {
+          rv -= jit;
+          base = 2.0 * (p.amp - kv) + jit;
+        }
+      }
+      kt[t * 64 + l] = (KT)rv;
+    }
+    base += shfl_xor_d(base, 16);
+    base += shfl_xor_d(base, 32);
   }
   mu_part += shfl_xor_d(mu_part, 16);
   mu_part += shfl_xor_d(mu_part, 32);
@@ -113,12 +187,16 @@ __global__ __launch_bounds__(256) void k_post16(PostArgs p) {
     if constexpr (F32) ((float*)p.mu)[my_row] = (float)(p.st->mean_y + mu_part);
     else ((double*)p.mu)[my_row] = p.st->mean_y + mu_part;
   }
+  // FP32 mode: the row constant of output row 4 (l/16) + i sits on lane 4 (l/16) + i
+  double base_o[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) base_o[i] = F32 ? __shfl(base, 4 * my_k + i, 64) : 0.0;
   if ((l & 15) == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int64_t r = F32 ? row0 + 4 * my_k + i : row0 + my_k + 4 * i;
       if (r < p.n_valid) {
-        double v = p.amp - sq[i];
+        double v = (F32 ? base_o[i] : p.amp) - sq[i];
         v = v > 0.0 ? v : 0.0;
         if constexpr (F32) {
           const float vf = (float)v;
@@ -189,6 +267,7 @@ hipError_t launch_posterior(const DevPtrs& P, const Layout& Lo, const GpConst& g
   a.Xo32 = P.Xo32;
   a.alpha = P.alpha;
   a.Bpk = P.Bpk;
+  a.K0 = P.K0;
   a.mu = P.mu;
   a.var = P.var;
   a.vslots = P.vslots;

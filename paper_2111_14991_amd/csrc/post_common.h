@@ -18,6 +18,7 @@ struct PostArgs {
   const float* Xo32;
   const double* alpha;
   const void* Bpk;
+  const double* K0;
   void* mu;
   void* var;
   VarSlot* vslots;

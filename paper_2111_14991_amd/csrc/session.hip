@@ -237,6 +237,7 @@ bool make_layout(const bo_problem& p, Layout* L) {
   o.off_alpha = take(np * 8);
   o.off_z = take(np * 8);
   o.off_Bpk = take(bpk_bytes(p.precision, (int)np));
+  o.off_K0 = take(p.precision == BO_FP32 ? np * np * 8 : 0);
   o.total = off;
   *L = o;
   return true;
@@ -265,6 +266,7 @@ DevPtrs carve(const Layout& o, uint8_t* b) {
   P.alpha = (double*)(b + o.off_alpha);
   P.z = (double*)(b + o.off_z);
   P.Bpk = b + o.off_Bpk;
+  P.K0 = o.prec == BO_FP32 ? (double*)(b + o.off_K0) : nullptr;
   return P;
 }
 
