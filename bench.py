@@ -30,6 +30,14 @@ sys.path.insert(0, ROOT)
 PEAK = {"bf16": 2500.0, "fp32": 157.3, "fp64": 78.6}  # dense TFLOP/s, MI355X
 HBM_GBS = 8000.0
 
+MULTI = {
+    "c4": "256 independent sessions (candidates log-uniform in [1e3, 2e5], 3-10 parameters, invalid U[0, 0.4], "
+          "10-220 observations), FP32 posterior, FP64 fit, one persistent graph-captured launch per step, "
+          "autotuned tile shapes",
+    "c5": "1024 live sessions (sizes as in c4, 10-200 initial observations), Poisson arrivals of step requests, "
+          "rank-1 append per request, 64 GB HBM admission budget, continuous batching over 3 launch streams",
+}
+
 WORKLOADS = {
     "c3": dict(fn="config_c3", precision="bf16x3", dtype="bf16", peak="bf16",
                desc="1,048,576-point 4^10 grid, 30% invalid, n=1000 observations, BF16X3 posterior"),
@@ -93,12 +101,231 @@ def cpu_baseline(s, n_unmasked: int, budget_s: float = 12.0):
             "step_s_estimate": t_step}
 
 
+def _post_flops(N_valid, n, d):
+    """Algorithmic flops of one posterior over N_valid candidates (see the
+    single-session roofline)."""
+    return float(N_valid) * (n * n + (3 * d + 12) * n + 2 * n)
+
+
+def _cpu_sessions(sessions, budget_s=12.0):
+    """FP64 oracle on this host over whole sessions of the population, in order,
+    until the budget is spent; returns (evals/s, cores, description)."""
+    import oracle
+    done_c, t_tot, k = 0, 0.0, 0
+    for s in sessions:
+        Xo = oracle.normalize_grid(s.levels, s.grid_index(s.obs_idx))
+        mask = (s.invalid | s.visited()).astype(bool)
+        pool = np.flatnonzero(~mask)
+        P = oracle.normalize_grid(s.levels, s.grid_index(pool))
+        t0 = time.perf_counter()
+        f = oracle.fit(Xo, s.y)
+        oracle.predict(f, P)
+        t_tot += time.perf_counter() - t0
+        done_c += pool.size
+        k += 1
+        if t_tot > budget_s:
+            break
+    return done_c / t_tot, oracle.threads(), f"FP64 oracle fit + posterior of the first {k} sessions " \
+        f"({done_c} candidates, {t_tot:.2f} s)"
+
+
+def bench_batched(args, torch, bo, W) -> int:
+    pop = W.config_c4(0)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    S = []
+    for s in pop:
+        x = bo.Session(s.N, s.d, 256, "fp32", device=dev)
+        x.set_grid(s.levels, s.cand, s.invalid)
+        S.append(x)
+    B = bo.Batch(S)
+    obs = [torch.as_tensor(s.obs_idx).to(dev) for s in pop]
+    ys = [torch.as_tensor(s.y).to(dev) for s in pop]
+    vis = [torch.as_tensor(s.visited()).to(dev) for s in pop]
+    acqs = [bo.AcqParams(mode=1, mu_s=float(np.mean(s.y[:s.n_init])), var_s_mean=0.0) for s in pop]
+    t0 = time.perf_counter()
+    cfg = B.tune(obs, ys, vis, acqs, reps=2)
+    t_tune = time.perf_counter() - t0
+    B.set_timing(True)
+    for _ in range(args.warmup):
+        res, _ = B.step(obs, ys, vis, acqs)
+    torch.cuda.synchronize()
+    lat, gms = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        res, ms = B.step(obs, ys, vis, acqs)
+        lat.append(time.perf_counter() - ts)
+        gms.append(ms)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert all(r.status == 0 for r in res), [r.status for r in res if r.status]
+    unmasked = sum(int(r.n_unmasked) for r in res)
+    ms_per_step = (t1 - t0) / args.steps * 1e3
+    # the plain path: the same sessions stepped one after another
+    for x, o, y_, v, a in zip(S, obs, ys, vis, acqs):
+        x.fit(o, y_)
+        x.acquire(v, a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for x, o, y_, v, a in zip(S, obs, ys, vis, acqs):
+        x.fit(o, y_)
+        x.acquire(v, a)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3
+    g = float(np.mean(gms))
+    flops = sum(_post_flops(int((s.invalid == 0).sum()), s.n, s.d) for s in pop)
+    achieved = flops / (g * 1e-3) / 1e12
+    line = {
+        "metric": "candidate posterior+acquisition evals/s; BO step p50/p99 latency",
+        "value": unmasked / (ms_per_step * 1e-3), "unit": "candidate-evals/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "c4: " + MULTI["c4"], "sessions": len(pop), "unmasked": unmasked,
+                   "candidates": int(sum(s.N for s in pop)), "tuned": cfg, "tune_s": t_tune},
+        "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
+        "graph_ms": g,
+        "plain_path": {"ms_per_round": plain_ms, "value": unmasked / (plain_ms * 1e-3),
+                       "speedup_batched": plain_ms / ms_per_step},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK["fp32"], "traffic": None, "kernel": "k_batch", "kernel_ms": g},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        v, cores, desc = _cpu_sessions(pop)
+        line["cpu_baseline"] = {"value": v, "unit": "candidate-evals/s", "cores": cores, "kind": "oracle",
+                                "sample": desc}
+    print(json.dumps(line), flush=True)
+    B.close()
+    for x in S:
+        x.close()
+    return 0
+
+
+def bench_serving(args, torch, bo, W) -> int:
+    pop = W.config_c5_population(0)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    srv = bo.Server(hbm_budget=64 << 30, max_batch=256, streams=3)
+    t0 = time.perf_counter()
+    sids = [srv.open(s.levels, s.obs_idx, s.y, N=s.N, cand=s.cand, invalid=s.invalid, n_max=256, precision="fp32")
+            for s in pop]
+    t_open = time.perf_counter() - t0
+    rng = np.random.Generator(np.random.PCG64(17))
+    acqs = [bo.AcqParams(mode=1, mu_s=float(np.mean(s.y[:s.n_init])), var_s_mean=0.0) for s in pop]
+    visited = [s.visited().astype(bool) for s in pop]
+    n_obs = [s.n for s in pop]
+    nxt = []
+    for s, v in zip(pop, visited):
+        pool = np.flatnonzero((s.invalid == 0) & ~v)
+        nxt.append(int(rng.choice(pool)))
+
+    def request(i):
+        s = pop[i]
+        idx = nxt[i]
+        y = float(s.observe(rng, np.array([idx]))[0])
+        visited[i][idx] = True
+        n_obs[i] += 1
+        return srv.submit(sids[i], idx, y, True, acqs[i])
+
+    def settle(i, r):
+        assert r.status == 0, r.status
+        nxt[i] = int(r.idx[0])  # closed loop: evaluate the EI choice next
+
+    # capacity: every session submits at once
+    t0 = time.perf_counter()
+    burst = [(i, request(i)) for i in range(len(pop))]
+    unm = 0
+    for i, t in burst:
+        r, _ = srv.wait(t)
+        settle(i, r)
+        unm += r.n_unmasked
+    t_burst = time.perf_counter() - t0
+    cap_rps = len(pop) / t_burst
+    # Poisson arrivals at 60% of that capacity, sessions chosen among the idle ones
+    rate = 0.6 * cap_rps
+    M = int(args.requests)
+    live = {}
+    idle = list(range(len(pop)))
+    lat, unmasked = [], 0
+    t_start = time.perf_counter()
+    t_next = t_start
+    sent = 0
+    while sent < M or live:
+        now = time.perf_counter()
+        if sent < M and now >= t_next and idle:
+            i = idle.pop(int(rng.integers(0, len(idle))))
+            live[request(i)] = i
+            sent += 1
+            t_next += float(rng.exponential(1.0 / rate))
+            continue
+        for t in [t for t in list(live) if srv.poll(t)]:
+            i = live.pop(t)
+            r, ms = srv.wait(t)
+            settle(i, r)
+            lat.append(ms)
+            unmasked += r.n_unmasked
+            if n_obs[i] < 256:  # a session retires when its fit is full
+                idle.append(i)
+    t_run = time.perf_counter() - t_start
+    st = srv.stats()
+    # the plain per-session path on the first 64 sessions, one request at a time
+    P = []
+    for s in pop[:64]:
+        x = bo.Session(s.N, s.d, 256, "fp32", device=dev)
+        x.set_grid(s.levels, s.cand, s.invalid)
+        o = list(s.obs_idx)
+        yv = list(s.y)
+        x.fit(np.array(o), np.array(yv))
+        P.append([x, o, yv, s.visited()])
+    plat, punm = [], 0
+    t0 = time.perf_counter()
+    for k in range(256):
+        i = k % 64
+        x, o, yv, v = P[i]
+        s = pop[i]
+        pool = np.flatnonzero((s.invalid == 0) & (v == 0))
+        idx = int(pool[k % pool.size])
+        ts = time.perf_counter()
+        o.append(idx)
+        yv.append(float(s.observe(rng, np.array([idx]))[0]))
+        v[idx] = 1
+        x.append(np.array(o), np.array(yv))
+        r = x.acquire(v, acqs[i])
+        plat.append((time.perf_counter() - ts) * 1e3)
+        punm += r.n_unmasked
+    t_plain = time.perf_counter() - t0
+    line = {
+        "metric": "candidate posterior+acquisition evals/s; BO step p50/p99 latency",
+        "value": unmasked / t_run, "unit": "candidate-evals/s",
+        "n_gpus": 1, "steps": len(lat), "warmup": len(pop), "ms_per_step": t_run / max(1, len(lat)) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "c5: " + MULTI["c5"], "sessions": len(pop), "arrival_rate_rps": rate,
+                   "open_s": t_open},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(np.mean(lat))},
+        "requests_per_s": len(lat) / t_run,
+        "burst_capacity_rps": cap_rps,
+        "server": st,
+        "plain_path": {"requests": len(plat), "value": punm / t_plain, "requests_per_s": len(plat) / t_plain,
+                       "latency_ms": {"p50": float(np.percentile(plat, 50)), "p99": float(np.percentile(plat, 99))}},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+    for x in P:
+        x[0].close()
+    srv.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + sorted(MULTI))
+    ap.add_argument("--requests", type=int, default=6000, help="c5: requests in the Poisson run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (reference for the "
@@ -122,6 +349,10 @@ def main() -> int:
     import paper_2111_14991_amd as bo
     from paper_2111_14991_amd import workloads as W
 
+    if args.workload == "c4":
+        return bench_batched(args, torch, bo, W)
+    if args.workload == "c5":
+        return bench_serving(args, torch, bo, W)
     wl = WORKLOADS[args.workload]
     s = getattr(W, wl["fn"])(0)
     dev = torch.device("cuda:0")

@@ -175,6 +175,19 @@ bo_status bo_set_candidates(bo_session* s, const void* X, int32_t x_is_f32,
  * Asynchronous; device-side errors surface at the next synchronizing call. */
 bo_status bo_gp_fit(bo_session* s, const int64_t* obs_idx, const double* y, int32_t n);
 
+/* Refit after one new observation (Section III-B), as a bordered rank-1
+ * extension of the device-resident factor: obs_idx and y (device, n entries)
+ * hold the current fit's n - 1 observations in the same order followed by the
+ * new one.  When the session holds a fit of n - 1 points and n <= 256, the
+ * new row of L and L^-1 is computed from L^-1 in O(n^2), alpha is recomputed
+ * and only the changed part of the packed operand is rewritten.  Otherwise,
+ * or when a pivot fails the test of the (n)-point factorization (the new
+ * pivot, or the smallest old one against the larger threshold), this is
+ * bo_gp_fit.  The outcome equals bo_gp_fit's on the same arrays up to
+ * rounding, with the same accepted jitter.  Asynchronous; errors as
+ * bo_gp_fit.  BF16X3 sessions always refit. */
+bo_status bo_gp_append(bo_session* s, const int64_t* obs_idx, const double* y, int32_t n);
+
 /* Synchronizing: fit status, accepted jitter, m and f_best.  alpha (host
  * double[n]) and Linv (host double[n*n], row-major lower triangle of L^-1)
  * are filled when non-NULL. */
@@ -209,6 +222,142 @@ bo_status bo_acquire_async(bo_session* s, const uint8_t* visited, const bo_acq_p
  * bo_set_timing, never on the step path. */
 bo_status bo_set_timing(bo_session* s, int32_t enable);
 bo_status bo_get_timing(bo_session* s, float* fit_ms, float* posterior_ms, float* acquire_ms);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many independent sessions advance one step together.
+ *
+ * One persistent kernel runs every session's FP64 fit (n <= 256), posterior
+ * tiles and acquisition chunks from a single work queue; the launch is
+ * captured once in a HIP graph (plan upload, kernel, result download) and
+ * replayed each step.  Per-session results equal those of bo_gp_fit +
+ * bo_acquire on the same session up to the summation order of the mean
+ * variance.  Sessions must be FP64 or FP32, have candidates set, and have no
+ * work pending on their own streams; the batch runs on its own stream.
+ * ---------------------------------------------------------------------- */
+typedef struct bo_batch bo_batch;
+
+/* Tile shapes and scheduling of the batched kernel. */
+typedef struct {
+  int32_t tile_rows;  /* candidates per wave in a posterior tile: 16 or 32 (32 applies where
+                         the kernel's LDS holds it, n_pad <= 128 for FP32) */
+  int32_t acq_chunk;  /* candidates per acquisition work item, a positive multiple of 2048 */
+  int32_t fit_order;  /* 0: sessions in order; 1: largest fit first */
+  int32_t reserved;
+} bo_batch_config;
+
+/* Device workspace bytes of a batch of `count` sessions (1..65536). */
+bo_status bo_batch_workspace_query(int32_t count, size_t* bytes);
+
+/* Bind `count` distinct sessions (host array of handles, kept by reference:
+ * they must outlive the batch) over a caller-owned, 256-byte-aligned device
+ * workspace.  stream: hipStream_t as void*; NULL creates a private blocking
+ * stream.  Default config {16, 8192, 1}. */
+bo_status bo_batch_create(bo_batch** out, bo_session* const* sessions, int32_t count, void* workspace,
+                          size_t bytes, void* stream);
+void bo_batch_destroy(bo_batch* b);
+
+bo_status bo_batch_set_config(bo_batch* b, const bo_batch_config* cfg);
+bo_status bo_batch_get_config(bo_batch* b, bo_batch_config* cfg);
+
+/* With timing on, bo_batch_step reports the graph's duration (HIP events on
+ * the batch stream). */
+bo_status bo_batch_set_timing(bo_batch* b, int32_t enable);
+
+/* One step of every session, synchronizing.  Host arrays of `count` entries:
+ * obs_idx[i], y[i] (device pointers, as bo_gp_fit), n[i] (1..min(n_max, 256)),
+ * visited[i] (device uint8[N_i] or NULL; visited itself may be NULL),
+ * params[i], out[i] (host).  Each out[i].status reports that session's
+ * outcome; the return value reports argument and runtime errors only.
+ * graph_ms (nullable) receives the graph's duration, -1 without timing.
+ * After the call each session holds the new fit, as after bo_gp_fit. */
+bo_status bo_batch_step(bo_batch* b, const int64_t* const* obs_idx, const double* const* y, const int32_t* n,
+                        const uint8_t* const* visited, const bo_acq_params* params, bo_acq_result* out,
+                        float* graph_ms);
+
+/* Autotuner: runs the step `reps` + 1 times for each tile shape / chunk /
+ * fit order of a fixed candidate set, keeps the configuration with the
+ * lowest median graph time, stores it in the batch and returns it in
+ * *chosen (nullable).  out receives the results of the last run. */
+bo_status bo_batch_tune(bo_batch* b, const int64_t* const* obs_idx, const double* const* y, const int32_t* n,
+                        const uint8_t* const* visited, const bo_acq_params* params, int32_t reps,
+                        bo_batch_config* chosen, bo_acq_result* out);
+
+/* ------------------------------------------------------------------------
+ * Serving form: live sessions, BO step requests arriving at any time.
+ *
+ * A request appends one evaluation to its session (bo_gp_append's rank-1
+ * extension of the device-resident factor; for an evaluation that failed,
+ * valid = 0, only the visited mark) and returns the step's result.  A
+ * scheduler thread gathers pending requests of idle sessions (one request in
+ * flight per session, oldest first) into launches of the batched persistent
+ * kernel on up to `streams` launch contexts, each with its own stream, so
+ * that requests arriving while launches run are admitted as soon as a context
+ * frees up and launches overlap on the device.  A session's device state is
+ * allocated when it fits in the memory budget; until then it waits, with its
+ * requests.  All entry points are thread-safe.
+ * ---------------------------------------------------------------------- */
+typedef struct bo_server bo_server;
+
+typedef struct {
+  size_t hbm_budget;       /* device bytes for session state (bo_server_session_bytes each) */
+  int32_t max_batch;       /* most requests in one launch, 1..4096 */
+  int32_t streams;         /* launches in flight at once, 1..8 */
+  bo_batch_config tiles;   /* tile shapes of the batched kernel */
+} bo_server_config;
+
+typedef struct {
+  int64_t steps_done;
+  int64_t launches;
+  int64_t sessions_resident;
+  int64_t sessions_waiting;  /* opened, waiting for memory */
+  int64_t pending;           /* requests not yet launched */
+  size_t bytes_in_use;
+  double mean_batch;         /* requests per launch */
+} bo_server_info;
+
+/* Device bytes one session of this problem holds while resident. */
+bo_status bo_server_session_bytes(const bo_problem* prob, size_t* bytes);
+
+/* Starts the scheduler on the current device.  The server allocates its
+ * launch contexts now and session state on admission (hipMalloc, outside the
+ * step path). */
+bo_status bo_server_create(bo_server** out, const bo_server_config* cfg);
+
+/* Refuses requests not yet launched (status BO_E_STATE), waits for launches
+ * in flight, frees everything. */
+void bo_server_destroy(bo_server* srv);
+
+/* Opens a session: problem (precision FP64 or FP32, n_max <= 256), GP
+ * parameters (NULL: defaults), the candidate grid as in bo_set_grid but with
+ * host arrays (levels[d]; cand[N] or NULL; invalid[N] or NULL) and n0 >= 1
+ * initial observations (host obs_idx, y).  *id identifies the session.  The
+ * session is set up now if it fits in the budget, otherwise when memory is
+ * freed.  BO_E_BUDGET when it alone exceeds the budget. */
+bo_status bo_server_open(bo_server* srv, const bo_problem* prob, const bo_gp_params* gp, const int32_t* levels,
+                         const int64_t* cand, const uint8_t* invalid, const int64_t* obs_idx, const double* y,
+                         int32_t n0, int32_t* id);
+
+/* Closes a session: its queued requests still run, then its memory returns
+ * to the budget (a session still waiting for memory is dropped at once and its
+ * requests finish with BO_E_STATE). */
+bo_status bo_server_close(bo_server* srv, int32_t id);
+
+/* Queues a step: evaluation `y` of candidate `idx` (valid != 0), or a failed
+ * evaluation of `idx` (valid = 0: visited mark only), then the acquisition
+ * with `acq`.  *ticket identifies the request.  Errors in the arguments are
+ * returned here; errors of the step are in the result's status. */
+bo_status bo_server_submit(bo_server* srv, int32_t id, int64_t idx, double y, int32_t valid,
+                           const bo_acq_params* acq, uint64_t* ticket);
+
+/* *done = 1 once the request's result is available. */
+bo_status bo_server_poll(bo_server* srv, uint64_t ticket, int32_t* done);
+
+/* Blocks until the request is done, returns its result and its latency from
+ * submission (ms, nullable), and forgets the ticket. */
+bo_status bo_server_wait(bo_server* srv, uint64_t ticket, bo_acq_result* out, double* latency_ms);
+
+/* Counters and occupancy of the server. */
+bo_status bo_server_stats(bo_server* srv, bo_server_info* out);
 
 #ifdef __cplusplus
 }

@@ -57,6 +57,22 @@ class bo_fit_info(C.Structure):
                 ("jitter", C.c_double), ("mean_y", C.c_double), ("f_best", C.c_double)]
 
 
+class bo_batch_config(C.Structure):
+    _fields_ = [("tile_rows", C.c_int32), ("acq_chunk", C.c_int32), ("fit_order", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class bo_server_config(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_batch", C.c_int32), ("streams", C.c_int32),
+                ("tiles", bo_batch_config)]
+
+
+class bo_server_info(C.Structure):
+    _fields_ = [("steps_done", C.c_int64), ("launches", C.c_int64), ("sessions_resident", C.c_int64),
+                ("sessions_waiting", C.c_int64), ("pending", C.c_int64), ("bytes_in_use", C.c_size_t),
+                ("mean_batch", C.c_double)]
+
+
 class BOError(RuntimeError):
     def __init__(self, status: int, where: str, msg: str):
         super().__init__(f"{where}: status {status}: {msg}")
@@ -78,12 +94,37 @@ _SIGS = {
     "bo_set_grid": (C.c_int, [_VP, _I32P, _I64P, _U8P, C.POINTER(C.c_int64)]),
     "bo_set_candidates": (C.c_int, [_VP, _VP, C.c_int32, _U8P, C.POINTER(C.c_int64)]),
     "bo_gp_fit": (C.c_int, [_VP, _I64P, _DP, C.c_int32]),
+    "bo_gp_append": (C.c_int, [_VP, _I64P, _DP, C.c_int32]),
     "bo_fit_read": (C.c_int, [_VP, C.POINTER(bo_fit_info), _DP, _DP]),
     "bo_posterior": (C.c_int, [_VP, _U8P, _DP, _DP, C.POINTER(C.c_double)]),
     "bo_acquire": (C.c_int, [_VP, _U8P, C.POINTER(bo_acq_params), C.POINTER(bo_acq_result)]),
     "bo_acquire_async": (C.c_int, [_VP, _U8P, C.POINTER(bo_acq_params), _VP]),
     "bo_set_timing": (C.c_int, [_VP, C.c_int32]),
     "bo_get_timing": (C.c_int, [_VP, C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+    "bo_batch_workspace_query": (C.c_int, [C.c_int32, C.POINTER(C.c_size_t)]),
+    "bo_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32, _VP, C.c_size_t,
+                                  _VP]),
+    "bo_batch_destroy": (None, [_VP]),
+    "bo_batch_set_config": (C.c_int, [_VP, C.POINTER(bo_batch_config)]),
+    "bo_batch_get_config": (C.c_int, [_VP, C.POINTER(bo_batch_config)]),
+    "bo_batch_set_timing": (C.c_int, [_VP, C.c_int32]),
+    "bo_batch_step": (C.c_int, [_VP, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
+                                C.POINTER(C.c_void_p), C.POINTER(bo_acq_params), C.POINTER(bo_acq_result),
+                                C.POINTER(C.c_float)]),
+    "bo_batch_tune": (C.c_int, [_VP, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_int32),
+                                C.POINTER(C.c_void_p), C.POINTER(bo_acq_params), C.c_int32,
+                                C.POINTER(bo_batch_config), C.POINTER(bo_acq_result)]),
+    "bo_server_session_bytes": (C.c_int, [C.POINTER(bo_problem), C.POINTER(C.c_size_t)]),
+    "bo_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(bo_server_config)]),
+    "bo_server_destroy": (None, [_VP]),
+    "bo_server_open": (C.c_int, [_VP, C.POINTER(bo_problem), C.POINTER(bo_gp_params), _VP, _VP, _VP, _VP, _VP,
+                                 C.c_int32, C.POINTER(C.c_int32)]),
+    "bo_server_close": (C.c_int, [_VP, C.c_int32]),
+    "bo_server_submit": (C.c_int, [_VP, C.c_int32, C.c_int64, C.c_double, C.c_int32, C.POINTER(bo_acq_params),
+                                   C.POINTER(C.c_uint64)]),
+    "bo_server_poll": (C.c_int, [_VP, C.c_uint64, C.POINTER(C.c_int32)]),
+    "bo_server_wait": (C.c_int, [_VP, C.c_uint64, C.POINTER(bo_acq_result), C.POINTER(C.c_double)]),
+    "bo_server_stats": (C.c_int, [_VP, C.POINTER(bo_server_info)]),
 }
 
 
@@ -268,6 +309,15 @@ class Session:
         self._keep = [oi, yy]  # alive until the next synchronizing call
         _check(lib().bo_gp_fit(self.h, _ptr(oi), _ptr(yy), int(oi.shape[0])), "bo_gp_fit")
 
+    def append(self, obs_idx, y):
+        """Refit after one new observation: obs_idx / y hold the current fit's
+        observations followed by the new one (bo_gp_append)."""
+        torch = self.torch
+        oi = self._d(obs_idx, torch.int64)
+        yy = self._d(y, torch.float64)
+        self._keep = [oi, yy]
+        _check(lib().bo_gp_append(self.h, _ptr(oi), _ptr(yy), int(oi.shape[0])), "bo_gp_append")
+
     def fit_read(self, want_alpha=True, want_linv=False):
         info = bo_fit_info()
         n = int(self._keep[0].shape[0]) if self._keep else 0
@@ -316,3 +366,159 @@ class Session:
         a = (acq or AcqParams(mode=0)).c()
         _check(lib().bo_acquire_async(self.h, _ptr(visited), C.byref(a), out_dev.data_ptr()),
                "bo_acquire_async")
+
+
+class Batch:
+    """Many sessions stepped together by one persistent, graph-captured launch
+    (bo_batch_*).  The sessions must outlive the batch."""
+
+    def __init__(self, sessions: Sequence[Session], device=None, stream=None):
+        torch = _torch()
+        self.torch = torch
+        self.sessions = list(sessions)
+        self.count = len(self.sessions)
+        self.device = self.sessions[0].device if device is None else torch.device(device)
+        nb = C.c_size_t()
+        _check(lib().bo_batch_workspace_query(self.count, C.byref(nb)), "bo_batch_workspace_query")
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        ws = (self.workspace.data_ptr() + 255) // 256 * 256
+        hs = (C.c_void_p * self.count)(*[s.h.value for s in self.sessions])
+        st = None if stream is None else stream.cuda_stream
+        h = C.c_void_p()
+        _check(lib().bo_batch_create(C.byref(h), hs, self.count, ws, nb.value, st), "bo_batch_create")
+        self.h = h
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().bo_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _args(self, obs, ys, visited, acqs):
+        torch = self.torch
+        k = self.count
+        oi = [_dev(o, torch.int64, torch, self.device) for o in obs]
+        yy = [_dev(v, torch.float64, torch, self.device) for v in ys]
+        vis = [None if v is None else _dev(v, torch.uint8, torch, self.device) for v in (visited or [None] * k)]
+        self._keep = [oi, yy, vis]
+        P = C.c_void_p * k
+        po = P(*[t.data_ptr() for t in oi])
+        py = P(*[t.data_ptr() for t in yy])
+        pv = P(*[0 if t is None else t.data_ptr() for t in vis])
+        pn = (C.c_int32 * k)(*[int(t.shape[0]) for t in oi])
+        acqs = acqs if isinstance(acqs, (list, tuple)) else [acqs or AcqParams(mode=0)] * k
+        pa = (bo_acq_params * k)(*[a.c() for a in acqs])
+        return po, py, pn, pv, pa
+
+    def set_config(self, tile_rows=16, acq_chunk=8192, fit_order=1):
+        c = bo_batch_config(tile_rows, acq_chunk, fit_order, 0)
+        _check(lib().bo_batch_set_config(self.h, C.byref(c)), "bo_batch_set_config")
+
+    def config(self):
+        c = bo_batch_config()
+        _check(lib().bo_batch_get_config(self.h, C.byref(c)), "bo_batch_get_config")
+        return {"tile_rows": c.tile_rows, "acq_chunk": c.acq_chunk, "fit_order": c.fit_order}
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().bo_batch_set_timing(self.h, 1 if enable else 0), "bo_batch_set_timing")
+
+    def step(self, obs, ys, visited=None, acqs=None):
+        """One step of every session; returns ([StepResult], graph_ms)."""
+        po, py, pn, pv, pa = self._args(obs, ys, visited, acqs)
+        out = (bo_acq_result * self.count)()
+        ms = C.c_float(-1.0)
+        _check(lib().bo_batch_step(self.h, po, py, pn, pv, pa, out, C.byref(ms)), "bo_batch_step")
+        return [_result(r) for r in out], ms.value
+
+    def tune(self, obs, ys, visited=None, acqs=None, reps=3):
+        """Autotune tile shapes on these inputs; returns the chosen config."""
+        po, py, pn, pv, pa = self._args(obs, ys, visited, acqs)
+        out = (bo_acq_result * self.count)()
+        c = bo_batch_config()
+        _check(lib().bo_batch_tune(self.h, po, py, pn, pv, pa, int(reps), C.byref(c), out), "bo_batch_tune")
+        return {"tile_rows": c.tile_rows, "acq_chunk": c.acq_chunk, "fit_order": c.fit_order}
+
+
+def server_session_bytes(N: int, d: int, n_max: int, precision="fp32") -> int:
+    p = bo_problem(int(N), int(d), int(n_max), PRECISIONS[precision] if isinstance(precision, str) else precision, 0)
+    out = C.c_size_t()
+    _check(lib().bo_server_session_bytes(C.byref(p), C.byref(out)), "bo_server_session_bytes")
+    return out.value
+
+
+class Server:
+    """Serving runtime (bo_server_*): sessions live on the device, step
+    requests are batched continuously by the library's scheduler thread."""
+
+    def __init__(self, hbm_budget: int = 64 << 30, max_batch: int = 256, streams: int = 2,
+                 tile_rows: int = 16, acq_chunk: int = 8192, fit_order: int = 1):
+        _torch()
+        cfg = bo_server_config(int(hbm_budget), int(max_batch), int(streams),
+                               bo_batch_config(tile_rows, acq_chunk, fit_order, 0))
+        h = C.c_void_p()
+        _check(lib().bo_server_create(C.byref(h), C.byref(cfg)), "bo_server_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().bo_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def open(self, levels, obs_idx, y, N=None, cand=None, invalid=None, n_max=220, precision="fp32",
+             gp: Optional[GpParams] = None) -> int:
+        lv = np.ascontiguousarray(levels, dtype=np.int32)
+        d = lv.shape[0]
+        if N is None:
+            N = int(np.prod(lv.astype(np.int64))) if cand is None else len(cand)
+        cd = None if cand is None else np.ascontiguousarray(cand, dtype=np.int64)
+        inv = None if invalid is None else np.ascontiguousarray(invalid, dtype=np.uint8)
+        oi = np.ascontiguousarray(obs_idx, dtype=np.int64)
+        yy = np.ascontiguousarray(y, dtype=np.float64)
+        prob = bo_problem(int(N), d, int(n_max), PRECISIONS[precision] if isinstance(precision, str) else precision,
+                          0)
+        g = (gp or GpParams()).c()
+        sid = C.c_int32()
+        _check(lib().bo_server_open(self.h, C.byref(prob), C.byref(g), lv.ctypes.data,
+                                    None if cd is None else cd.ctypes.data, None if inv is None else inv.ctypes.data,
+                                    oi.ctypes.data, yy.ctypes.data, int(oi.shape[0]), C.byref(sid)),
+               "bo_server_open")
+        return sid.value
+
+    def close_session(self, sid: int):
+        _check(lib().bo_server_close(self.h, int(sid)), "bo_server_close")
+
+    def submit(self, sid: int, idx: int, y: float, valid: bool = True, acq: Optional[AcqParams] = None) -> int:
+        a = (acq or AcqParams(mode=0)).c()
+        t = C.c_uint64()
+        _check(lib().bo_server_submit(self.h, int(sid), int(idx), float(y), 1 if valid else 0, C.byref(a),
+                                      C.byref(t)), "bo_server_submit")
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = C.c_int32()
+        _check(lib().bo_server_poll(self.h, C.c_uint64(ticket), C.byref(d)), "bo_server_poll")
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        """Returns (StepResult, latency_ms)."""
+        r = bo_acq_result()
+        ms = C.c_double()
+        _check(lib().bo_server_wait(self.h, C.c_uint64(ticket), C.byref(r), C.byref(ms)), "bo_server_wait")
+        return _result(r), ms.value
+
+    def stats(self) -> dict:
+        i = bo_server_info()
+        _check(lib().bo_server_stats(self.h, C.byref(i)), "bo_server_stats")
+        return {k: getattr(i, k) for k, _ in bo_server_info._fields_}

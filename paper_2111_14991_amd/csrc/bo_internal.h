@@ -27,6 +27,7 @@ struct DevState {
   int32_t need_retry;   // large fit: pivot failed at `attempt`, host retries
   double mean_y, f_best, jitter;
   double lambda, var_mean;
+  double min_piv;       // smallest accepted Cholesky pivot of the current factor
   int64_t n_unmasked;
   int32_t post_status;  // posterior / lambda status
   int32_t pad0;
@@ -108,6 +109,8 @@ hipError_t launch_grid_setup(const DevPtrs& P, const Layout& Lo, const int32_t* 
                              const uint8_t* invalid, int64_t N, hipStream_t st);
 hipError_t launch_fit_small(const DevPtrs& P, const Layout& Lo, const GpConst& g, const int64_t* obs_idx,
                             const double* y_in, int n, hipStream_t st);
+hipError_t launch_fit_append(const DevPtrs& P, const Layout& Lo, const GpConst& g, const int64_t* obs_idx,
+                             const double* y_in, int n, hipStream_t st);
 hipError_t launch_fit_large(const DevPtrs& P, const Layout& Lo, const GpConst& g, const int64_t* obs_idx,
                             const double* y_in, int n, int first_attempt, hipStream_t st);
 hipError_t launch_posterior(const DevPtrs& P, const Layout& Lo, const GpConst& g, int n, int64_t n_valid,

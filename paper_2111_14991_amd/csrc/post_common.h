@@ -1,5 +1,6 @@
-// Shared by the posterior kernels: launch arguments and the last-workgroup
-// reduction of the mean variance and the exploration factor.
+// Shared by the posterior kernels: launch arguments, the per-wave posterior of
+// the FP64 / FP32 modes, and the last-workgroup reduction of the mean variance
+// and the exploration factor.
 #pragma once
 #include "bo_internal.h"
 #include "bo_device.h"
@@ -8,6 +9,7 @@ namespace bo {
 
 struct PostArgs {
   int n, n_pad, d, nu2;
+  int ld;  // row stride of K0
   double inv_l, amp;
   int64_t n_valid, N_pad;
   const double* X64;
@@ -19,6 +21,7 @@ struct PostArgs {
   const double* alpha;
   const void* Bpk;
   const double* K0;
+  const double* Linv;  // row stride ld
   void* mu;
   void* var;
   VarSlot* vslots;
@@ -27,7 +30,8 @@ struct PostArgs {
 };
 
 // Last workgroup of a posterior launch: fixed-order reduction of the slots,
-// mean variance and exploration factor (Section III-F).
+// mean variance and exploration factor (Section III-F).  Every thread of the
+// workgroup calls it; s_sum / s_cnt hold blockDim.x entries.
 __device__ inline void finish_lambda(const PostArgs& p, int nslots, double* s_sum, int64_t* s_cnt) {
   const int t = threadIdx.x, nt = blockDim.x;
   const int per = (nslots + nt - 1) / nt;
@@ -74,6 +78,345 @@ __device__ inline void finish_lambda(const PostArgs& p, int nslots, double* s_su
     }
     st->ticket_post = 0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Posterior of RB blocks of 16 compacted candidates by one wave, FP64 or FP32
+// mode (Section III-G).
+//
+// The wave generates the FP64 cross-covariance k* = amp Matern(|x_c - x_i|)
+// against every observation, accumulates the mean mu = m + k*^T alpha in FP64
+// and parks the FP64 operand of the variance contraction in LDS (kt: RB
+// regions of n_pad * 16 doubles) in the A-operand order of a 16x16x4
+// matrix-core product: entry (row r, observation i) of block b at
+// kt[b][(i/4) * 64 + 16 (i%4) + r].  The contraction W = (operand) L^-T runs
+// on the matrix cores against the packed lower-triangular L^-1, column block
+// by column block, skipping the all-zero tiles above the diagonal; each B
+// fragment is loaded once for the RB row blocks.
+//
+// FP64 mode: the operand is k* and var = amp - |W|^2.
+//
+// FP32 mode (compensated, with an FP64 fallback): rounding k* and L^-1 to
+// FP32 leaves errors proportional to |k*| |L^-1|, large next to the variance
+// near the data.  The operand is instead the residual of k* after projecting
+// out the nearest observation p: with K = K_nn + delta I,
+// c = k*_p / K_pp and r = k* - c K e_p (so r_p = 0), L^-1 K e_p = L^T e_p
+// gives exactly
+//     k*^T K^-1 k* = k*_p^2 / K_pp + |L^-1 r|^2,
+//     var = amp - k*_p^2 / K_pp - |L^-1 r|^2,
+// whose first part is exact in FP64; only |L^-1 r|^2 goes through FP32
+// products (summed over 16 observations, chunks added in FP64), and |r|
+// shrinks with the distance to the data.  Where var is still small next to
+// |L^-1 r|^2 (more than a quarter of it: cancellation would amplify the FP32
+// rounding past what the acquisitions tolerate), the wave recomputes
+// |L^-1 r|^2 for that block of 16 rows with FP64 products against L^-1 itself.
+//
+// Writes mu and var (FP64 or FP32) of the rows below n_valid and returns, on
+// lane 0, the sum and count of the variances of the rows not yet evaluated.
+// Element (i, j) of L^-1 as a B operand, zero outside the lower triangle of
+// the current fit.
+__device__ __forceinline__ double linv_b(const PostArgs& p, int row, int col) {
+  return (col <= row && row < p.n) ? p.Linv[(size_t)row * p.ld + col] : 0.0;
+}
+
+template <bool F32, int RB>
+__device__ void post16_wave(const PostArgs& p, int64_t row0, double* kt, double* part_out, int64_t* cnt_out) {
+  const int l = threadIdx.x & 63;
+  const int nt4 = p.n_pad >> 2;
+  const int my_k = l >> 4;
+  double base[RB];  // FP32 mode: amp - k*_p^2 / K_pp of the lane's row
+  double mu_part[RB];
+
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    double* ktb = kt + (size_t)b * nt4 * 64;
+    const int64_t my_row = row0 + 16 * b + (l & 15);
+    double xr[kMaxD];
+#pragma unroll
+    for (int j = 0; j < kMaxD; ++j) xr[j] = j < p.d ? p.X64[(int64_t)j * p.N_pad + my_row] : 0.0;
+    double mp = 0.0, bs = 0.0;
+    if constexpr (!F32) {
+      for (int t = 0; t < nt4; ++t) {
+        const int i = 4 * t + my_k;
+        double kv = 0.0;
+        if (i < p.n) {
+          const double* xo = p.Xo64 + (size_t)i * kMaxD;
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < kMaxD; ++j) {
+            if (j < p.d) {
+              const double df = xr[j] - xo[j];
+              s += df * df;
+            }
+          }
+          kv = p.amp * matern64(p.nu2, sqrt(s), p.inv_l);
+          mp += kv * p.alpha[i];
+        }
+        ktb[t * 64 + l] = kv;
+      }
+    } else {
+      // nearest observation of the row: the four lanes of a row scan disjoint
+      // observations, then compare (distance, index) pairs
+      double best = __builtin_inf();
+      int bi = 0;
+      for (int t = 0; t < nt4; ++t) {
+        const int i = 4 * t + my_k;
+        if (i < p.n) {
+          const double* xo = p.Xo64 + (size_t)i * kMaxD;
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < kMaxD; ++j) {
+            if (j < p.d) {
+              const double df = xr[j] - xo[j];
+              s += df * df;
+            }
+          }
+          if (s < best) {
+            best = s;
+            bi = i;
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 16; m <= 32; m <<= 1) {
+        const double ob = shfl_xor_d(best, m);
+        const int oi = __shfl_xor(bi, m, 64);
+        if (ob < best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      // k*_p from the same distance the scan found, on every lane of the row
+      const double kp = p.amp * matern64(p.nu2, sqrt(best), p.inv_l);
+      const double kpp = p.amp + p.st->jitter;
+      const double c = kp / kpp;
+      bs = p.amp - kp * c;
+      const double* krow = p.K0 + (size_t)bi * p.ld;
+      for (int t = 0; t < nt4; ++t) {
+        const int i = 4 * t + my_k;
+        double rv = 0.0;
+        if (i < p.n) {
+          const double* xo = p.Xo64 + (size_t)i * kMaxD;
+          double s = 0.0;
+#pragma unroll
+          for (int j = 0; j < kMaxD; ++j) {
+            if (j < p.d) {
+              const double df = xr[j] - xo[j];
+              s += df * df;
+            }
+          }
+          const double kv = p.amp * matern64(p.nu2, sqrt(s), p.inv_l);
+          mp += kv * p.alpha[i];
+          rv = i == bi ? 0.0 : kv - c * krow[i];
+        }
+        ktb[t * 64 + l] = rv;
+      }
+    }
+    mp += shfl_xor_d(mp, 16);
+    mp += shfl_xor_d(mp, 32);
+    mu_part[b] = mp;
+    base[b] = bs;
+  }
+
+  // variance contraction on the matrix cores
+  double sq[RB][4];
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sq[b][i] = 0.0;
+  const int JB = p.n_pad >> 4;
+  for (int J = 0; J < JB; ++J) {
+    const int tmax = 4 * J + 3;
+    const size_t fbase = (size_t)2 * J * (J + 1);
+    if constexpr (F32) {
+      const float* B = (const float*)p.Bpk + fbase * 64 + l;
+      double a64[RB][4];
+      f32x4 acc[RB];
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        acc[b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a64[b][i] = 0.0;
+      }
+      for (int t = 0; t <= tmax; ++t) {
+        const float bv = B[(size_t)t * 64];
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)kt[((size_t)b * nt4 + t) * 64 + l], bv, acc[b], 0,
+                                                        0, 0);
+        if ((t & 3) == 3) {
+#pragma unroll
+          for (int b = 0; b < RB; ++b) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a64[b][i] += (double)acc[b][i];
+            acc[b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+          }
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sq[b][i] += a64[b][i] * a64[b][i];
+    } else {
+      const double* B = (const double*)p.Bpk + fbase * 64 + l;
+      f64x4 acc[RB];
+#pragma unroll
+      for (int b = 0; b < RB; ++b) acc[b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+      for (int t = 0; t <= tmax; ++t) {
+        const double bv = B[(size_t)t * 64];
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(kt[((size_t)b * nt4 + t) * 64 + l], bv, acc[b], 0, 0, 0);
+      }
+#pragma unroll
+      for (int b = 0; b < RB; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sq[b][i] += acc[b][i] * acc[b][i];
+    }
+  }
+
+  double part = 0.0;
+  int64_t cnt = 0;
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    const int64_t brow0 = row0 + 16 * b;
+    // sum over the 16 columns held by the lanes of each quarter-wave
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double v = sq[b][i];
+      v += shfl_xor_d(v, 1);
+      v += shfl_xor_d(v, 2);
+      v += shfl_xor_d(v, 4);
+      v += shfl_xor_d(v, 8);
+      sq[b][i] = v;
+    }
+    // FP32 mode: the row constant of output row 4 (l/16) + i sits on lane 4 (l/16) + i
+    double base_o[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) base_o[i] = F32 ? __shfl(base[b], 4 * my_k + i, 64) : 0.0;
+    if constexpr (F32) {
+      // rows whose variance is dominated by cancellation: FP64 products
+      bool flag = false;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = brow0 + 4 * my_k + i;
+        flag |= r < p.n_valid && sq[b][i] > 4.0 * (base_o[i] - sq[b][i]);
+      }
+      if (__any(flag)) {
+        double* ktb = kt + (size_t)b * nt4 * 64;
+        double s64[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int J = 0; J < JB; ++J) {
+          f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+          for (int t = 0; t <= 4 * J + 3; ++t) {
+            const double bv = linv_b(p, 16 * J + (l & 15), 4 * t + my_k);
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ktb[t * 64 + l], bv, acc, 0, 0, 0);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) s64[i] += acc[i] * acc[i];
+        }
+        // the FP64 product orders rows as l/16 + 4i; move them to the FP32 order 4(l/16) + i
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          double v = s64[i];
+          v += shfl_xor_d(v, 1);
+          v += shfl_xor_d(v, 2);
+          v += shfl_xor_d(v, 4);
+          v += shfl_xor_d(v, 8);
+          s64[i] = v;
+        }
+        // row q = 4a + i (FP32 order) is FP64 row a' + 4i' with a' = q % 4, i' = q / 4,
+        // held in register i' by the lanes with l / 16 = a'
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int q = 4 * my_k + i;
+          const int src = 16 * (q & 3);
+          double v = 0.0;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const double t = __shfl(s64[k], src, 64);
+            v = (q >> 2) == k ? t : v;
+          }
+          sq[b][i] = v;
+        }
+      }
+    }
+    const int64_t my_row = brow0 + (l & 15);
+    if (l < 16 && my_row < p.n_valid) {
+      if constexpr (F32) ((float*)p.mu)[my_row] = (float)(p.st->mean_y + mu_part[b]);
+      else ((double*)p.mu)[my_row] = p.st->mean_y + mu_part[b];
+    }
+    // output register i of lane l holds row 4(l/16) + i for the FP32 product
+    // and row l/16 + 4i for the FP64 product
+    if ((l & 15) == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t r = F32 ? brow0 + 4 * my_k + i : brow0 + my_k + 4 * i;
+        if (r < p.n_valid) {
+          double v = (F32 ? base_o[i] : p.amp) - sq[b][i];
+          v = v > 0.0 ? v : 0.0;
+          if constexpr (F32) {
+            const float vf = (float)v;
+            ((float*)p.var)[r] = vf;
+            v = (double)vf;
+          } else {
+            ((double*)p.var)[r] = v;
+          }
+          const bool vis = p.visited && p.visited[p.orig[r]];
+          if (!vis) {
+            part += v;
+            ++cnt;
+          }
+        }
+      }
+    }
+  }
+  // the four quarter-wave leaders hold rows in increasing order
+  part += __shfl_down(part, 16, 64);
+  part += __shfl_down(part, 32, 64);
+  cnt += __shfl_down(cnt, 16, 64);
+  cnt += __shfl_down(cnt, 32, 64);
+  *part_out = part;
+  *cnt_out = cnt;
+}
+
+// Rows per workgroup and row blocks per wave of the single-session FP64 / FP32
+// posterior: up to 4 waves of 16 rows within 128 KB of LDS.
+inline int post16_waves(int prec, int n_pad) {
+  (void)prec;  // both modes park FP64 operands
+  for (int W = 4; W >= 1; W >>= 1)
+    if ((size_t)W * n_pad * 16 * sizeof(double) <= 128 * 1024) return W;
+  return 1;
+}
+
+// Launch arguments of a session's posterior.
+inline PostArgs make_post_args(const DevPtrs& P, const Layout& Lo, const GpConst& g, int n, int64_t n_valid,
+                               const uint8_t* visited, const AcqArgs& acq) {
+  PostArgs a{};
+  a.n = n;
+  a.n_pad = n_pad_of(n);
+  a.ld = Lo.n_max_pad;
+  a.d = Lo.d;
+  a.nu2 = g.nu2;
+  a.inv_l = 1.0 / g.l;
+  a.amp = g.amp;
+  a.n_valid = n_valid;
+  a.N_pad = Lo.N_pad;
+  a.X64 = P.X64;
+  a.X32 = P.X32;
+  a.orig = P.orig;
+  a.visited = visited;
+  a.Xo64 = P.Xo64;
+  a.Xo32 = P.Xo32;
+  a.alpha = P.alpha;
+  a.Bpk = P.Bpk;
+  a.K0 = P.K0;
+  a.Linv = P.Linv;
+  a.mu = P.mu;
+  a.var = P.var;
+  a.vslots = P.vslots;
+  a.st = P.st;
+  a.acq = acq;
+  return a;
 }
 
 }  // namespace bo

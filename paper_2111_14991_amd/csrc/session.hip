@@ -10,6 +10,7 @@
 #include <string>
 
 #include "bo_internal.h"
+#include "session_impl.h"
 
 using namespace bo;
 
@@ -17,37 +18,14 @@ namespace bo {
 int64_t acquire_blocks(int64_t n_valid);
 }
 
-struct bo_session {
-  bo_problem prob;
-  GpConst gp;
-  Layout lo;
-  DevPtrs P;
-  hipStream_t stream;
-  uint8_t* ws;
-  size_t ws_bytes;
-  int64_t n_valid;
-  int have_cand;
-  int have_fit;
-  int n;
-  int fit_attempt;
-  bo_acq_result* hres;  // pinned host copy of the device result
-  DevState* hstate;     // pinned host copy of the device state
-  int timing;
-  hipEvent_t ev[6];     // fit begin/end, posterior begin/end, acquire begin/end
-  int ev_have[3];
-};
 
 namespace {
 
-thread_local std::string g_err;
-
 bo_status fail(bo_status s, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vset_error(fmt, ap);
   va_end(ap);
-  g_err = buf;
   return s;
 }
 
@@ -96,22 +74,7 @@ bo_status settle_fit(bo_session* s, bool* retried) {
   return BO_OK;
 }
 
-bo_status check_acq(const bo_acq_params* a, AcqArgs* out) {
-  if (!a) return fail(BO_E_INVALID_ARG, "acq params are NULL");
-  if (a->mode != 0 && a->mode != 1) return fail(BO_E_INVALID_ARG, "acq mode %d is not 0 or 1", a->mode);
-  if (a->acq_bits & ~7u) return fail(BO_E_INVALID_ARG, "unknown acquisition bits 0x%x", a->acq_bits);
-  if (a->mode == 0 && !std::isfinite(a->lambda_const))
-    return fail(BO_E_INVALID_ARG, "lambda_const is not finite");
-  if (a->mode == 1 && !(a->mu_s > 0.0 && std::isfinite(a->mu_s)))
-    return fail(BO_E_INVALID_ARG, "contextual variance needs mu_s > 0");
-  if (a->mode == 1 && !std::isfinite(a->var_s_mean)) return fail(BO_E_INVALID_ARG, "var_s_mean is not finite");
-  out->mode = a->mode;
-  out->bits = a->acq_bits ? a->acq_bits : 7u;
-  out->lambda_const = a->lambda_const;
-  out->mu_s = a->mu_s;
-  out->var_s_mean = a->var_s_mean;
-  return BO_OK;
-}
+bo_status check_acq(const bo_acq_params* a, AcqArgs* out) { return acq_params_check(a, out); }
 
 bo_status step_ready(bo_session* s) {
   if (!s) return fail(BO_E_INVALID_ARG, "session is NULL");
@@ -187,6 +150,43 @@ bo_status set_candidates(bo_session* s, const int32_t* levels, const int64_t* ca
 
 // ---------------------------------------------------------------- layout --
 namespace bo {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void vset_error(const char* fmt, va_list ap) {
+  char buf[512];
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  g_err = buf;
+}
+
+bo_status set_error(bo_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vset_error(fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+const char* last_error_text() { return g_err.c_str(); }
+
+bo_status acq_params_check(const bo_acq_params* a, AcqArgs* out) {
+  if (!a) return set_error(BO_E_INVALID_ARG, "acq params are NULL");
+  if (a->mode != 0 && a->mode != 1) return set_error(BO_E_INVALID_ARG, "acq mode %d is not 0 or 1", a->mode);
+  if (a->acq_bits & ~7u) return set_error(BO_E_INVALID_ARG, "unknown acquisition bits 0x%x", a->acq_bits);
+  if (a->mode == 0 && !std::isfinite(a->lambda_const)) return set_error(BO_E_INVALID_ARG, "lambda_const is not finite");
+  if (a->mode == 1 && !(a->mu_s > 0.0 && std::isfinite(a->mu_s)))
+    return set_error(BO_E_INVALID_ARG, "contextual variance needs mu_s > 0");
+  if (a->mode == 1 && !std::isfinite(a->var_s_mean)) return set_error(BO_E_INVALID_ARG, "var_s_mean is not finite");
+  out->mode = a->mode;
+  out->bits = a->acq_bits ? a->acq_bits : 7u;
+  out->lambda_const = a->lambda_const;
+  out->mu_s = a->mu_s;
+  out->var_s_mean = a->var_s_mean;
+  return BO_OK;
+}
+
 
 size_t bpk_bytes(int prec, int n_pad) {
   if (prec == BO_BF16X3) {
@@ -277,7 +277,7 @@ extern "C" {
 
 const char* bo_version(void) { return "bo-mi355x 0.1 (gfx950)"; }
 
-const char* bo_last_error(void) { return g_err.c_str(); }
+const char* bo_last_error(void) { return last_error_text(); }
 
 bo_status bo_workspace_query(const bo_problem* prob, size_t* bytes) {
   if (!bytes) return fail(BO_E_INVALID_ARG, "bytes is NULL");
@@ -379,6 +379,27 @@ bo_status bo_gp_fit(bo_session* s, const int64_t* obs_idx, const double* y, int3
   return BO_OK;
 }
 
+bo_status bo_gp_append(bo_session* s, const int64_t* obs_idx, const double* y, int32_t n) {
+  if (!s) return fail(BO_E_INVALID_ARG, "session is NULL");
+  if (!s->have_cand) return fail(BO_E_STATE, "no candidate set");
+  if (n < 1) return fail(BO_E_STATE, "a fit needs at least one observation (n = %d)", n);
+  if (n > s->prob.n_max) return fail(BO_E_INVALID_ARG, "n = %d exceeds n_max = %d", n, s->prob.n_max);
+  if (!obs_idx || !y) return fail(BO_E_INVALID_ARG, "obs_idx or y is NULL");
+  const bool bordered = s->have_fit && s->n == n - 1 && n <= kSmallFitMax;
+  s->n = n;
+  s->fit_attempt = 0;
+  MARK(s, 0);
+  if (bordered)
+    HIP_TRY(launch_fit_append(s->P, s->lo, s->gp, obs_idx, y, n, s->stream));
+  else if (n <= kSmallFitMax)
+    HIP_TRY(launch_fit_small(s->P, s->lo, s->gp, obs_idx, y, n, s->stream));
+  else
+    HIP_TRY(launch_fit_large(s->P, s->lo, s->gp, obs_idx, y, n, 0, s->stream));
+  MARK(s, 1);
+  s->have_fit = 1;
+  return BO_OK;
+}
+
 bo_status bo_fit_read(bo_session* s, bo_fit_info* info, double* alpha, double* Linv) {
   if (!s) return fail(BO_E_INVALID_ARG, "session is NULL");
   if (!s->have_fit) return fail(BO_E_STATE, "no fit");
@@ -395,10 +416,10 @@ bo_status bo_fit_read(bo_session* s, bo_fit_info* info, double* alpha, double* L
     info->mean_y = h.mean_y;
     info->f_best = h.f_best;
   }
-  const int n = s->n, np = n_pad_of(n);
+  const int n = s->n;
   if (alpha) HIP_TRY(hipMemcpy(alpha, s->P.alpha, sizeof(double) * n, hipMemcpyDeviceToHost));
   if (Linv) {
-    HIP_TRY(hipMemcpy2D(Linv, sizeof(double) * n, s->P.Linv, sizeof(double) * np, sizeof(double) * n, n,
+    HIP_TRY(hipMemcpy2D(Linv, sizeof(double) * n, s->P.Linv, sizeof(double) * s->lo.n_max_pad, sizeof(double) * n, n,
                         hipMemcpyDeviceToHost));
     // only the lower triangle of L^-1 is kept on the device
     for (int i = 0; i < n; ++i)
