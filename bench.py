@@ -326,6 +326,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + sorted(MULTI))
     ap.add_argument("--requests", type=int, default=6000, help="c5: requests in the Poisson run")
+    ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default=None,
+                    help="c1-c3: posterior arithmetic other than the workload's own")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (reference for the "
@@ -353,7 +355,11 @@ def main() -> int:
         return bench_batched(args, torch, bo, W)
     if args.workload == "c5":
         return bench_serving(args, torch, bo, W)
-    wl = WORKLOADS[args.workload]
+    wl = dict(WORKLOADS[args.workload])
+    if args.precision and args.precision != wl["precision"]:
+        wl.update(precision=args.precision, dtype={"bf16x3": "bf16"}.get(args.precision, args.precision),
+                  peak={"bf16x3": "bf16"}.get(args.precision, args.precision),
+                  desc=wl["desc"].rsplit(",", 1)[0] + f", {args.precision.upper()} posterior")
     s = getattr(W, wl["fn"])(0)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

@@ -212,10 +212,18 @@ __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s
   constexpr int S = 4096 / NT;
   const int tt = threadIdx.x;
   const int w = tt >> 6, q = tt & 63, r0 = S * w;
+  // colbuf[0..1]: the current column (double buffered); xbuf[0..1]: the current
+  // row of the inverse; the padding column T of s1 holds 1 / L_qq.  The step
+  // count is bound by VALU instructions per wave (each costs 4 cycles) and
+  // LDS round trips, so a step issues all its reads at once, has no branch
+  // (a failed pivot is recorded and reported after the loop) and forms
+  // 1 / pivot from the broadcast pivot with v_rcp_f64 and two Newton steps.
   double av[S], lv[S], xv[S];
 #pragma unroll
   for (int i = 0; i < S; ++i) av[i] = a.A[tix(a, k, k, r0 + i, q)];
   const double thr = (double)a.n * 2.220446049250313e-16 * (a.amp + delta);
+  double my_piv = 1.0;
+  bool bad = false;
   for (int c = 0; c < T; ++c) {
     double* col = colbuf[c & 1];
     if (q == c) {
@@ -223,34 +231,34 @@ __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s
       for (int i = 0; i < S; ++i) col[r0 + i] = av[i];
     }
     __syncthreads();
+    double cv[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) cv[i] = col[r0 + i];
     const double piv = col[c];
+    const double cq = col[q];
     const double lim = (k * T + c) < a.n ? thr : 0.0;
-    if (!(piv > lim) || !(piv < INFINITY)) return true;
+    bad |= !(piv > lim) || !(piv < INFINITY);
     if ((k * T + c) < a.n) *pmin = fmin(*pmin, piv);
-    if (r0 + S - 1 > c) {
-      // unconditional strip read, then selects: no lane-dependent branch, so
-      // the LDS reads issue together
-      double cv[S];
+    my_piv = q == c ? piv : my_piv;
+    double rp = __builtin_amdgcn_rcp(piv);
+    rp = fma(rp, fma(-piv, rp, 1.0), rp);
+    rp = fma(rp, fma(-piv, rp, 1.0), rp);
+    // columns q > c take the update on every row: the entries above the
+    // diagonal are never read, so they need no mask
+    const double cqs = q > c ? cq * rp : 0.0;
 #pragma unroll
-      for (int i = 0; i < S; ++i) cv[i] = col[r0 + i];
-      const double cqs = col[q] / piv;
-      const bool live = q > c;
-#pragma unroll
-      for (int i = 0; i < S; ++i) {
-        const double t = av[i] - cv[i] * cqs;
-        av[i] = (live && r0 + i >= q) ? t : av[i];
-      }
-    }
-    if (q == c) {
-      const double sq = sqrt(piv);
-      const double inv_sq = 1.0 / sq;
-#pragma unroll
-      for (int i = 0; i < S; ++i) {
-        const int r = r0 + i;
-        lv[i] = r > c ? av[i] * inv_sq : (r == c ? sq : 0.0);
-      }
-    }
+    for (int i = 0; i < S; ++i) av[i] = fma(-cv[i], cqs, av[i]);
   }
+  if (bad) return true;  // uniform: every thread saw the same pivots
+  // column q of L: A_rq / sqrt(pivot_q) below the diagonal
+  const double sq = sqrt(my_piv);
+  const double inv_sq = 1.0 / sq;
+#pragma unroll
+  for (int i = 0; i < S; ++i) {
+    const int r = r0 + i;
+    lv[i] = r > q ? av[i] * inv_sq : (r == q ? sq : 0.0);
+  }
+  if (w == 0) s1[q][T] = inv_sq;  // 1 / L_qq for the inverse
 #pragma unroll
   for (int i = 0; i < S; ++i) xv[i] = (r0 + i == q) ? 1.0 : 0.0;
   for (int r = 0; r < T; ++r) {
@@ -270,15 +278,13 @@ __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s
       double cv[S];
 #pragma unroll
       for (int i = 0; i < S; ++i) cv[i] = col[r0 + i];
-      const double x = xr[q] / col[r];
+      const double x = xr[q] * s1[r][T];
+      // L is zero above the diagonal, so rows before r are left unchanged
 #pragma unroll
-      for (int i = 0; i < S; ++i) {
-        const int rr = r0 + i;
-        const double t = xv[i] - cv[i] * x;
-        xv[i] = rr == r ? x : (rr > r ? t : xv[i]);
-      }
+      for (int i = 0; i < S; ++i) xv[i] = (r0 + i == r) ? x : fma(-cv[i], x, xv[i]);
     }
   }
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < S; ++i) {
     s1[r0 + i][q] = lv[i];

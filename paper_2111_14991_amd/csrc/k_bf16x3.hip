@@ -32,6 +32,10 @@ constexpr int kThreads = 512;
 constexpr int kWaves = kThreads / 64;
 constexpr int kQ = 32 / kWaves;  // column blocks per wave (n <= 1024)
 constexpr int kChunk = 64;  // observations per LDS chunk (4 k-steps of 16)
+// row pitch of the observation coordinates in LDS: 17 floats, so that the 16
+// observations a quarter-wave reads in the distance products fall in
+// distinct banks (a pitch of 16 puts them in two)
+constexpr int kXoPitch = kMaxD + 1;
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -57,7 +61,7 @@ struct __align__(16) ChunkBuf {
 
 struct __align__(16) Smem {
   ChunkBuf buf[2];
-  float xo[kMaxN * kMaxD];  // observation coordinates, zero-padded
+  float xo[kMaxN * kXoPitch];  // observation coordinates, zero-padded
   float xn[kMaxN];          // their squared norms
   double alpha[kMaxN];
   float sq[kWaves][kRows];
@@ -86,13 +90,13 @@ __global__ __launch_bounds__(kThreads) void k_post_bf16x3(PostArgs p, int ntiles
 
   for (int e = tid; e < p.n_pad * kMaxD; e += kThreads) {
     const int i = e / kMaxD, j = e % kMaxD;
-    S.xo[e] = (i < p.n && j < p.d) ? p.Xo32[(size_t)i * kMaxD + j] : 0.f;
+    S.xo[i * kXoPitch + j] = (i < p.n && j < p.d) ? p.Xo32[(size_t)i * kMaxD + j] : 0.f;
   }
   for (int i = tid; i < p.n_pad; i += kThreads) S.alpha[i] = i < p.n ? p.alpha[i] : 0.0;
   __syncthreads();
   for (int i = tid; i < p.n_pad; i += kThreads) {
     float s = 0.f;
-    for (int j = 0; j < kMaxD; ++j) s = fmaf(S.xo[i * kMaxD + j], S.xo[i * kMaxD + j], s);
+    for (int j = 0; j < kMaxD; ++j) s = fmaf(S.xo[i * kXoPitch + j], S.xo[i * kXoPitch + j], s);
     S.xn[i] = s;
   }
 
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void k_post_bf16x3(PostArgs p, int ntiles
       const int obs = c * kChunk + ob * 16 + (lane & 15);
 #pragma unroll
       for (int s = 0; s < KS; ++s)
-        d = __builtin_amdgcn_mfma_f32_16x16x4f32(S.xo[obs * kMaxD + 4 * s + (lane >> 4)], bx[s], d, 0, 0, 0);
+        d = __builtin_amdgcn_mfma_f32_16x16x4f32(S.xo[obs * kXoPitch + 4 * s + (lane >> 4)], bx[s], d, 0, 0, 0);
       return d;
     };
     // Matern, mean, split and store of the four values of block ob; output

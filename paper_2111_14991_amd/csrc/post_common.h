@@ -238,20 +238,29 @@ __device__ void post16_wave(const PostArgs& p, int64_t row0, double* kt, double*
 #pragma unroll
         for (int i = 0; i < 4; ++i) a64[b][i] = 0.0;
       }
-      for (int t = 0; t <= tmax; ++t) {
-        const float bv = B[(size_t)t * 64];
+      // groups of four k-steps (tmax + 1 is a multiple of 4), the B fragments
+      // of the next group loaded while this one runs
+      float bq[4], bn[4];
 #pragma unroll
-        for (int b = 0; b < RB; ++b)
-          acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)kt[((size_t)b * nt4 + t) * 64 + l], bv, acc[b], 0,
-                                                        0, 0);
-        if ((t & 3) == 3) {
+      for (int u = 0; u < 4; ++u) bq[u] = B[(size_t)u * 64];
+      for (int t0 = 0; t0 <= tmax; t0 += 4) {
+        const bool more = t0 + 4 <= tmax;
 #pragma unroll
-          for (int b = 0; b < RB; ++b) {
+        for (int u = 0; u < 4; ++u) bn[u] = B[(size_t)(more ? t0 + 4 + u : u) * 64];  // in bounds either way
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a64[b][i] += (double)acc[b][i];
-            acc[b] = (f32x4){0.f, 0.f, 0.f, 0.f};
-          }
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int b = 0; b < RB; ++b)
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)kt[((size_t)b * nt4 + t0 + u) * 64 + l], bq[u],
+                                                          acc[b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a64[b][i] += (double)acc[b][i];
+          acc[b] = (f32x4){0.f, 0.f, 0.f, 0.f};
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) bq[u] = bn[u];
       }
 #pragma unroll
       for (int b = 0; b < RB; ++b)
@@ -262,11 +271,21 @@ __device__ void post16_wave(const PostArgs& p, int64_t row0, double* kt, double*
       f64x4 acc[RB];
 #pragma unroll
       for (int b = 0; b < RB; ++b) acc[b] = (f64x4){0.0, 0.0, 0.0, 0.0};
-      for (int t = 0; t <= tmax; ++t) {
-        const double bv = B[(size_t)t * 64];
+      double bq[4], bn[4];
 #pragma unroll
-        for (int b = 0; b < RB; ++b)
-          acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(kt[((size_t)b * nt4 + t) * 64 + l], bv, acc[b], 0, 0, 0);
+      for (int u = 0; u < 4; ++u) bq[u] = B[(size_t)u * 64];
+      for (int t0 = 0; t0 <= tmax; t0 += 4) {
+        const bool more = t0 + 4 <= tmax;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) bn[u] = B[(size_t)(more ? t0 + 4 + u : u) * 64];  // in bounds either way
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int b = 0; b < RB; ++b)
+            acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(kt[((size_t)b * nt4 + t0 + u) * 64 + l], bq[u], acc[b],
+                                                          0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) bq[u] = bn[u];
       }
 #pragma unroll
       for (int b = 0; b < RB; ++b)
