@@ -208,8 +208,9 @@ bo_status bo_acquire(bo_session* s, const uint8_t* visited, const bo_acq_params*
                      bo_acq_result* out);
 
 /* Same as bo_acquire without waiting: *out_dev (device) is written on the
- * session stream.  Jitter escalation of a large fit (n > 256) is not retried
- * on this path; out_dev->status reports BO_E_NOT_PD instead. */
+ * session stream.  A fit of more than 128 observations by bo_gp_fit runs on
+ * the multi-workgroup path, whose jitter escalation is driven by the host:
+ * it is not retried here, and out_dev->status reports BO_E_NOT_PD instead. */
 bo_status bo_acquire_async(bo_session* s, const uint8_t* visited, const bo_acq_params* params,
                            bo_acq_result* out_dev);
 

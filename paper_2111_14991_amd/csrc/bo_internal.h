@@ -13,7 +13,8 @@ namespace bo {
 constexpr int kMaxD = 16;
 constexpr int kMaxN = 1024;
 constexpr int kTile = 32;           // fit tile edge (FP64)
-constexpr int kSmallFitMax = 256;   // n above this uses the multi-workgroup fit
+constexpr int kSmallFitMax = 256;   // most observations of the one-workgroup fit (batched, served, append)
+constexpr int kPlainSmallMax = 128; // a single session's fit above this uses the multi-workgroup fit
 constexpr int kAcqThreads = 256;
 constexpr int kAcqPerThread = 8;
 

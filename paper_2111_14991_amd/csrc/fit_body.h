@@ -176,25 +176,38 @@ __device__ void op_build(const FitArgs& a, int ti, int tj, double delta, double*
   __syncthreads();
 }
 
-// C (global tile) = init - sign * A B^T (NT) or A B (NN), A and B in LDS.
-// init is the current C when `accumulate`, else zero.
+// C (global tile) = init - sign * A B^T (NT) or A B (NN), A and B in LDS;
+// init is the current C when `accumulate`, else zero.  FP64 16x16x4 matrix-
+// core products: wave w (thread tt = 64 w + l) computes rows 16w..16w+15 as
+// four 16x16 output tiles; the A fragment of k-step t is A[16w + l%16][4t +
+// l/16], the B fragment of tile j is B^T or B at [4t + l/16][16j + l%16], and
+// output register i of lane l is row l/16 + 4i, column l%16.
 template <bool NT>
 __device__ void op_gemm(double* C, const FitArgs& a, int ti, int tj, const Tile& A, const Tile& B, bool accumulate,
                         double sign, int tt) {
-  const int w = tt >> 6, c = tt & 63;
-  double acc[16];
+  const int w = tt >> 6, l = tt & 63;
+  const int r = l & 15, kq = l >> 4;
+  f64x4 acc[4];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.0;
-  for (int k = 0; k < T; ++k) {
-    const double bv = NT ? B[c][k] : B[k][c];
+  for (int j = 0; j < 4; ++j) acc[j] = (f64x4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int t = 0; t < T / 4; ++t) {
+    const int kk = 4 * t + kq;
+    const double av = A[16 * w + r][kk];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = fma(A[16 * w + i][k], bv, acc[i]);
+    for (int j = 0; j < 4; ++j) {
+      const double bv = NT ? B[16 * j + r][kk] : B[kk][16 * j + r];
+      acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[j], 0, 0, 0);
+    }
   }
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const size_t ix = tix(a, ti, tj, 16 * w + i, c);
-    const double base = accumulate ? C[ix] : 0.0;
-    C[ix] = base - sign * acc[i];
+  for (int j = 0; j < 4; ++j) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const size_t ix = tix(a, ti, tj, 16 * w + kq + 4 * i, 16 * j + r);
+      const double base = accumulate ? C[ix] : 0.0;
+      C[ix] = base - sign * acc[j][i];
+    }
   }
 }
 

@@ -64,7 +64,7 @@ bo_status settle_fit(bo_session* s, bool* retried) {
   *retried = false;
   bo_status rc = sync_state(s);
   if (rc != BO_OK) return rc;
-  while (s->hstate->status == BO_E_NOT_PD && s->hstate->need_retry && s->n > kSmallFitMax) {
+  while (s->hstate->status == BO_E_NOT_PD && s->hstate->need_retry && s->large_fit) {
     s->fit_attempt += 1;
     HIP_TRY(launch_fit_large(s->P, s->lo, s->gp, nullptr, nullptr, s->n, s->fit_attempt, s->stream));
     rc = sync_state(s);
@@ -369,8 +369,10 @@ bo_status bo_gp_fit(bo_session* s, const int64_t* obs_idx, const double* y, int3
   if (!obs_idx || !y) return fail(BO_E_INVALID_ARG, "obs_idx or y is NULL");
   s->n = n;
   s->fit_attempt = 0;
+  // one session: the multi-workgroup fit is faster above kPlainSmallMax
+  s->large_fit = n > kPlainSmallMax;
   MARK(s, 0);
-  if (n <= kSmallFitMax)
+  if (!s->large_fit)
     HIP_TRY(launch_fit_small(s->P, s->lo, s->gp, obs_idx, y, n, s->stream));
   else
     HIP_TRY(launch_fit_large(s->P, s->lo, s->gp, obs_idx, y, n, 0, s->stream));
@@ -388,10 +390,11 @@ bo_status bo_gp_append(bo_session* s, const int64_t* obs_idx, const double* y, i
   const bool bordered = s->have_fit && s->n == n - 1 && n <= kSmallFitMax;
   s->n = n;
   s->fit_attempt = 0;
+  s->large_fit = !bordered && n > kPlainSmallMax;
   MARK(s, 0);
   if (bordered)
     HIP_TRY(launch_fit_append(s->P, s->lo, s->gp, obs_idx, y, n, s->stream));
-  else if (n <= kSmallFitMax)
+  else if (!s->large_fit)
     HIP_TRY(launch_fit_small(s->P, s->lo, s->gp, obs_idx, y, n, s->stream));
   else
     HIP_TRY(launch_fit_large(s->P, s->lo, s->gp, obs_idx, y, n, 0, s->stream));
@@ -473,7 +476,7 @@ bo_status bo_acquire(bo_session* s, const uint8_t* visited, const bo_acq_params*
     if (rc != BO_OK) return rc;
     HIP_TRY(hipMemcpyAsync(s->hres, s->P.res, sizeof(bo_acq_result), hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
-    if (!(s->hres->status == BO_E_NOT_PD && s->n > kSmallFitMax)) break;
+    if (!(s->hres->status == BO_E_NOT_PD && s->large_fit)) break;
     bool retried;
     rc = settle_fit(s, &retried);
     if (rc != BO_OK) return rc;

@@ -20,6 +20,7 @@ struct bo_session {
   int have_fit;
   int n;
   int fit_attempt;
+  int large_fit;        // the current fit runs on the multi-workgroup path (host jitter retries)
   bo_acq_result* hres;  // pinned host copy of the device result
   bo::DevState* hstate;     // pinned host copy of the device state
   int timing;
