@@ -133,9 +133,10 @@ def bench_batched(args, torch, bo, W) -> int:
     pop = W.config_c4(0)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    prec = args.precision or "fp32"
     S = []
     for s in pop:
-        x = bo.Session(s.N, s.d, 256, "fp32", device=dev)
+        x = bo.Session(s.N, s.d, 256, prec, device=dev)
         x.set_grid(s.levels, s.cand, s.invalid)
         S.append(x)
     B = bo.Batch(S)
@@ -180,15 +181,16 @@ def bench_batched(args, torch, bo, W) -> int:
         "metric": "candidate posterior+acquisition evals/s; BO step p50/p99 latency",
         "value": unmasked / (ms_per_step * 1e-3), "unit": "candidate-evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
-        "config": {"workload": "c4: " + MULTI["c4"], "sessions": len(pop), "unmasked": unmasked,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": "c4: " + MULTI["c4"].replace("FP32 posterior", prec.upper() + " posterior"),
+                   "sessions": len(pop), "unmasked": unmasked,
                    "candidates": int(sum(s.N for s in pop)), "tuned": cfg, "tune_s": t_tune},
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3)},
         "graph_ms": g,
         "plain_path": {"ms_per_round": plain_ms, "value": unmasked / (plain_ms * 1e-3),
                        "speedup_batched": plain_ms / ms_per_step},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["fp32"], "traffic": None, "kernel": "k_batch", "kernel_ms": g},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK[prec], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK[prec], "traffic": None, "kernel": "k_batch", "kernel_ms": g},
         "cpu_baseline": None,
     }
     if not args.no_cpu:
@@ -206,9 +208,10 @@ def bench_serving(args, torch, bo, W) -> int:
     pop = W.config_c5_population(0)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    prec = args.precision or "fp32"
     srv = bo.Server(hbm_budget=64 << 30, max_batch=256, streams=3)
     t0 = time.perf_counter()
-    sids = [srv.open(s.levels, s.obs_idx, s.y, N=s.N, cand=s.cand, invalid=s.invalid, n_max=256, precision="fp32")
+    sids = [srv.open(s.levels, s.obs_idx, s.y, N=s.N, cand=s.cand, invalid=s.invalid, n_max=256, precision=prec)
             for s in pop]
     t_open = time.perf_counter() - t0
     rng = np.random.Generator(np.random.PCG64(17))
@@ -272,7 +275,7 @@ def bench_serving(args, torch, bo, W) -> int:
     # the plain per-session path on the first 64 sessions, one request at a time
     P = []
     for s in pop[:64]:
-        x = bo.Session(s.N, s.d, 256, "fp32", device=dev)
+        x = bo.Session(s.N, s.d, 256, prec, device=dev)
         x.set_grid(s.levels, s.cand, s.invalid)
         o = list(s.obs_idx)
         yv = list(s.y)
@@ -299,8 +302,9 @@ def bench_serving(args, torch, bo, W) -> int:
         "metric": "candidate posterior+acquisition evals/s; BO step p50/p99 latency",
         "value": unmasked / t_run, "unit": "candidate-evals/s",
         "n_gpus": 1, "steps": len(lat), "warmup": len(pop), "ms_per_step": t_run / max(1, len(lat)) * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
-        "config": {"workload": "c5: " + MULTI["c5"], "sessions": len(pop), "arrival_rate_rps": rate,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": "c5: " + MULTI["c5"] + f", {prec.upper()} posterior", "sessions": len(pop),
+                   "arrival_rate_rps": rate,
                    "open_s": t_open},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "mean": float(np.mean(lat))},

@@ -81,6 +81,43 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
   return __shfl_xor(v, m, 64);
 }
 
+// A wave-uniform value the compiler cannot prove uniform (read through a
+// pointer chosen at run time, or passed to a called function) moved to
+// scalar registers: each 32-bit word is taken from the first active lane.
+template <typename T>
+__device__ __forceinline__ T uni(T v) {
+  static_assert(sizeof(T) % 4 == 0, "32-bit words");
+  union {
+    T v;
+    int w[sizeof(T) / 4];
+  } u;
+  u.v = v;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) u.w[i] = __builtin_amdgcn_readfirstlane(u.w[i]);
+  return u.v;
+}
+
+// A device pointer known to address global memory (HBM): loads through it
+// are global loads (addressed by a scalar base and a per-lane offset, counted
+// by the vector memory counter only) rather than flat ones.
+template <typename T>
+using gptr_t = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr_t<T> gptr(T* p) {
+  return (gptr_t<T>)p;
+}
+
+// Raw buffer over `bytes` bytes of device memory (gfx9 descriptor: no
+// swizzle, no format; reads past the end return zero).  Loads through it take
+// a per-lane offset and a scalar offset, so a sequence of loads at uniform
+// distances costs scalar adds only.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, 0x00020000);
+}
+__device__ __forceinline__ double buffer_load_f64(__amdgpu_buffer_rsrc_t r, int lane_off, int uniform_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, lane_off, uniform_off, 0));
+}
+
 // Last-block ticket: returns true in exactly one workgroup of the launch,
 // after every workgroup has published its partial with a device-scope fence.
 __device__ __forceinline__ bool last_block(uint32_t* ticket, int* s_flag) {

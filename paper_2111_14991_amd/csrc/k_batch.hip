@@ -130,11 +130,30 @@ __device__ void post_tile(const BatchSession& S, int t, unsigned char* s_raw, do
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   double part = 0.0;
   int64_t cnt = 0;
+  if (!F32 && p.n_pad <= 16 * kRegJB) {
+    double* xs = (double*)s_raw;
+    stage_obs(p, xs, xs + 16 * kRegJB * kObsPitch);
+  }
   if (w < S.waves) {
     double* kt = (double*)s_raw + (size_t)w * S.rb * (p.n_pad >> 2) * 64;
     const int64_t row0 = (int64_t)t * S.rows + (int64_t)w * 16 * S.rb;
-    if (S.rb == 2) post16_wave<F32, 2>(p, row0, kt, &part, &cnt);
-    else post16_wave<F32, 1>(p, row0, kt, &part, &cnt);
+    if (!F32 && p.n_pad <= 16 * kRegJB) {
+      // register-resident FP64 posterior, one block of 16 rows at a time,
+      // observations staged in LDS by post_tile
+      const double* xs = (const double*)s_raw;
+      const double* as = xs + 16 * kRegJB * kObsPitch;
+      for (int b = 0; b < S.rb; ++b) {
+        double pb;
+        int64_t cb;
+        post16_wave_reg_any(p, row0 + 16 * b, xs, as, &pb, &cb);
+        part += pb;
+        cnt += cb;
+      }
+    } else if (S.rb == 2) {
+      post16_wave<F32, 2>(p, row0, kt, &part, &cnt);
+    } else {
+      post16_wave<F32, 1>(p, row0, kt, &part, &cnt);
+    }
   }
   if (l == 0) {
     s_wsum[w] = part;
@@ -250,12 +269,18 @@ __global__ void k_batch_clear(BatchSync* sync, int cap, BatchCtl* ctl) {
 
 constexpr size_t kBatchLds = kSmallLdsBytes;
 static_assert(kBatchLds >= 2 * kBThreads * sizeof(double), "finish_lambda scratch");
+static_assert(kBatchLds >= kStageBytes, "staged observations");
 
 // Posterior tile shape of one session: row blocks per wave and active waves,
 // within the kernel's LDS (each wave parks rb * n_pad * 16 operand entries).
 void tile_shape(int f32, int n_pad, int want_rb, int* rb, int* waves) {
-  (void)f32;  // both modes park FP64 operands
-  const size_t esz = 8;
+  if (!f32 && n_pad <= 16 * kRegJB) {
+    // the register-resident FP64 posterior parks nothing in LDS
+    *rb = want_rb == 2 ? 2 : 1;
+    *waves = kBWaves;
+    return;
+  }
+  const size_t esz = 8;  // both modes park FP64 operands
   *rb = 1;
   if (want_rb == 2 && (size_t)kBWaves * 2 * n_pad * 16 * esz <= kBatchLds) *rb = 2;
   int w = kBWaves;

@@ -398,6 +398,164 @@ __device__ void post16_wave(const PostArgs& p, int64_t row0, double* kt, double*
   *cnt_out = cnt;
 }
 
+constexpr int kRegJB = 16;     // n_pad <= 256 takes the register-resident FP64 posterior
+constexpr int kObsPitch = kMaxD + 1;  // LDS row pitch of the staged observations
+
+// Stages the observation coordinates (n_pad rows, pitch kObsPitch, zero past
+// the d-th) and alpha (n_pad, zero past n) of a fit into LDS for
+// post16_wave_reg; every thread of the workgroup calls it.  The odd pitch puts
+// the four observations a wave reads at once in different banks.
+__device__ inline void stage_obs(const PostArgs& p, double* xs, double* as) {
+  for (int e = threadIdx.x; e < p.n_pad * kObsPitch; e += blockDim.x) {
+    const int i = e / kObsPitch, j = e - i * kObsPitch;
+    const double v = p.Xo64[i * kMaxD + (j < kMaxD ? j : kMaxD - 1)];
+    xs[e] = j < p.d ? v : 0.0;
+  }
+  for (int i = threadIdx.x; i < p.n_pad; i += blockDim.x) {
+    const double v = p.alpha[i];
+    as[i] = i < p.n ? v : 0.0;
+  }
+  __syncthreads();
+}
+
+// FP64 posterior of 16 candidates by one wave for n_pad = 16 JB, with the
+// contraction in k-outer order: lane l generates its A element
+// k*(row l%16, observation 4t + l/16) once per k-step t and feeds it to every
+// column block J >= t/4 (the others are zero above the diagonal), whose
+// accumulators stay in registers.  The observations (xs, as) come from LDS
+// as stage_obs leaves them; the candidate's first DM coordinates (DM >= d)
+// from HBM.  The shape is a template parameter, so every step is
+// straight-line code: the B loads of its live blocks, the kernel value, their
+// MFMAs.  Same outputs and slot partial as post16_wave<false>.
+template <int JB, int DM>
+__device__ void post16_wave_reg(const PostArgs& p, int64_t row0, const double* xs, const double* as,
+                                double* part_out, int64_t* cnt_out) {
+  static_assert(JB >= 1 && JB <= kRegJB && DM <= kMaxD, "shape");
+  const int l = threadIdx.x & 63;
+  const int my_k = l >> 4;
+  // every field below is the same across the wave; in the batched kernel the
+  // session is chosen at run time, so say so to keep them in scalar registers
+  row0 = uni(row0);
+  const int n = uni(p.n), d = uni(p.d);
+  const bool nu5 = uni(p.nu2) == 5;
+  const double amp = uni(p.amp);
+  // Matern (Section III-B) as (1 + rho (1 + c2 rho)) exp(-rho), rho = c1 r
+  const double c1 = (nu5 ? 2.23606797749978969641 : 1.73205080756887729353) * uni(p.inv_l);
+  const double c2 = nu5 ? 1.0 / 3.0 : 0.0;
+  const int64_t n_valid = uni(p.n_valid), N_pad = uni(p.N_pad);
+  const auto X64 = gptr(uni(p.X64));
+  const auto orig = gptr(uni(p.orig));
+  const auto visited = gptr(uni(p.visited));
+  const auto mu = gptr((double*)uni(p.mu));
+  const auto var = gptr((double*)uni(p.var));
+  const double mean_y = uni(p.st)->mean_y;
+  const int64_t my_row = row0 + (l & 15);
+  double xr[DM];
+#pragma unroll
+  for (int j = 0; j < DM; ++j) {
+    const double v = X64[(int64_t)(j < d ? j : d - 1) * N_pad + my_row];
+    xr[j] = j < d ? v : 0.0;
+  }
+  // packed B of 16 JB column blocks: 2 JB (JB + 1) tiles of 64 lanes
+  const __amdgpu_buffer_rsrc_t rB = buffer_of(uni(p.Bpk), 2 * JB * (JB + 1) * 64 * (int)sizeof(double));
+  f64x4 acc[JB];
+#pragma unroll
+  for (int J = 0; J < JB; ++J) acc[J] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  double mp = 0.0;
+  // phase J0 covers k-steps 4 J0 .. 4 J0 + 3, whose B values are nonzero in
+  // blocks J0 .. JB - 1 only; the phases are unrolled, so each one's loads
+  // and MFMAs are a fixed sequence
+#pragma unroll
+  for (int J0 = 0; J0 < JB; ++J0) {
+#pragma unroll 1
+    for (int tt = 0; tt < 4; ++tt) {
+      const int t = 4 * J0 + tt;
+      double bq[JB];
+#pragma unroll
+      for (int J = J0; J < JB; ++J) bq[J] = buffer_load_f64(rB, l * 8, (2 * J * (J + 1) + t) * 64 * 8);
+      const int i = 4 * t + my_k;
+      const double* xo = xs + i * kObsPitch;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int j = 0; j < DM; j += 2) {
+        const double e0 = xr[j] - xo[j];
+        s0 = fma(e0, e0, s0);
+        if (j + 1 < DM) {
+          const double e1 = xr[j + 1] - xo[j + 1];
+          s1 = fma(e1, e1, s1);
+        }
+      }
+      const double rho = c1 * sqrt(s0 + s1);
+      double kv = amp * (fma(rho, fma(c2, rho, 1.0), 1.0) * exp(-rho));
+      kv = i < n ? kv : 0.0;
+      mp = fma(kv, as[i], mp);
+#pragma unroll
+      for (int J = J0; J < JB; ++J) acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv, bq[J], acc[J], 0, 0, 0);
+    }
+  }
+  mp += shfl_xor_d(mp, 16);
+  mp += shfl_xor_d(mp, 32);
+  // output register i of lane l: row l/16 + 4i, column l%16 of block J
+  double sq[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int J = 0; J < JB; ++J)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sq[i] += acc[J][i] * acc[J][i];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double v = sq[i];
+    v += shfl_xor_d(v, 1);
+    v += shfl_xor_d(v, 2);
+    v += shfl_xor_d(v, 4);
+    v += shfl_xor_d(v, 8);
+    sq[i] = v;
+  }
+  double part = 0.0;
+  int64_t cnt = 0;
+  if (l < 16 && my_row < n_valid) mu[my_row] = mean_y + mp;
+  if ((l & 15) == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = row0 + my_k + 4 * i;
+      if (r < n_valid) {
+        double v = amp - sq[i];
+        v = v > 0.0 ? v : 0.0;
+        var[r] = v;
+        if (!(visited && visited[orig[r]])) {
+          part += v;
+          ++cnt;
+        }
+      }
+    }
+  }
+  part += __shfl_down(part, 16, 64);
+  part += __shfl_down(part, 32, 64);
+  cnt += __shfl_down(cnt, 16, 64);
+  cnt += __shfl_down(cnt, 32, 64);
+  *part_out = part;
+  *cnt_out = cnt;
+}
+
+// Calls post16_wave_reg with the shape of p (n_pad <= 16 kRegJB).
+__device__ inline void post16_wave_reg_any(const PostArgs& p, int64_t row0, const double* xs, const double* as,
+                                           double* part_out, int64_t* cnt_out) {
+  const int jb = uni(p.n_pad) >> 4;
+  const bool small_d = uni(p.d) <= 8;
+#define BO_REG_CASE(JBV)                                                          \
+  case JBV:                                                                       \
+    if (small_d) post16_wave_reg<JBV, 8>(p, row0, xs, as, part_out, cnt_out);     \
+    else post16_wave_reg<JBV, kMaxD>(p, row0, xs, as, part_out, cnt_out);         \
+    break;
+  switch (jb) {
+    BO_REG_CASE(4) BO_REG_CASE(8) BO_REG_CASE(12) BO_REG_CASE(16)
+    default: break;
+  }
+#undef BO_REG_CASE
+}
+
+// LDS bytes of stage_obs for n_pad <= 16 kRegJB.
+constexpr size_t kStageBytes = (size_t)16 * kRegJB * (kObsPitch + 1) * sizeof(double);
+
 // Rows per workgroup and row blocks per wave of the single-session FP64 / FP32
 // posterior: up to 4 waves of 16 rows within 128 KB of LDS.
 inline int post16_waves(int prec, int n_pad) {
