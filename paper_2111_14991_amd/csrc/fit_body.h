@@ -211,99 +211,199 @@ __device__ void op_gemm(double* C, const FitArgs& a, int ti, int tj, const Tile&
   }
 }
 
+// Wave-local LDS ordering: the wave's earlier LDS writes are seen by its
+// later reads (the other waves of the workgroup are not involved).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// 16 x 16 x 16 FP64 products of LDS blocks on the matrix cores, one wave.
+// Result layout (as the 16x16x4 product leaves it): register i of lane l is
+// row l/16 + 4i, column l%16.
+// acc + A[ra.., ca..] * B[rb.., cb..]^T
+__device__ __forceinline__ f64x4 mm16_nt(const Tile& A, int ra, int ca, const Tile& B, int rb, int cb, f64x4 acc,
+                                         int lane) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ra + (lane & 15)][ca + 4 * s + (lane >> 4)],
+                                               B[rb + (lane & 15)][cb + 4 * s + (lane >> 4)], acc, 0, 0, 0);
+  return acc;
+}
+// acc + A[ra.., ca..] * B[rb.., cb..]
+__device__ __forceinline__ f64x4 mm16_nn(const Tile& A, int ra, int ca, const Tile& B, int rb, int cb, f64x4 acc,
+                                         int lane) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ra + (lane & 15)][ca + 4 * s + (lane >> 4)],
+                                               B[rb + 4 * s + (lane >> 4)][cb + (lane & 15)], acc, 0, 0, 0);
+  return acc;
+}
+// acc + A[ra.., ca..] * M, M in registers in the result layout above (its
+// register s is exactly the B operand of k-step s)
+__device__ __forceinline__ f64x4 mm16_nr(const Tile& A, int ra, int ca, const f64x4& M, f64x4 acc, int lane) {
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ra + (lane & 15)][ca + 4 * s + (lane >> 4)], M[s], acc, 0, 0, 0);
+  return acc;
+}
+
 // Diagonal tile k: Cholesky with the pivot test, then the inverse of the
-// factor, with the tile held in registers by all NT threads of the workgroup
-// (thread 64 w + q owns rows S w .. S w + S - 1 of column q, S = 4096 / NT).
-// One barrier per column: the owner of column c publishes it through LDS
-// (double-buffered), every thread updates its rows; the inverse is a
-// right-looking forward substitution on the identity.  The factor is left in
-// s1 and its inverse in s0.  Returns true when a pivot fails (the same answer
-// in every thread).
+// factor.  The pivots form one sequential chain, so the tile is factored by a
+// single wave, blocked in 16 x 16 sub-blocks (kb = 0..3):
+//  - the diagonal sub-block is held in registers (lane l: column l%16, rows
+//    l/16 + 4i) and factored column by column, the values each step needs
+//    passed between lanes by permutes; its inverse follows by forward
+//    substitution on the identity, row by row;
+//  - the panel L_ib = A_ib L_bb^-T and the trailing update
+//    A_ij -= L_ib L_jb^T are 16x16x16 FP64 matrix-core products;
+//  - the off-diagonal inverse blocks X_ij = -X_ii sum_m L_im X_mj, i > j.
+// The pivot test: a pivot of a row below n must exceed n eps (amp + delta)
+// and be finite (padding rows: positive).  The factor (zeros above the
+// diagonal) is left in s1 and its inverse in s0.  Returns true when a pivot
+// fails, in every thread; *pmin takes the smallest pivot of the rows below n.
 template <int NT>
 __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s1, double (*colbuf)[64],
                         double (*xbuf)[64], double* pmin) {
-  constexpr int S = 4096 / NT;
   const int tt = threadIdx.x;
-  const int w = tt >> 6, q = tt & 63, r0 = S * w;
-  // colbuf[0..1]: the current column (double buffered); xbuf[0..1]: the current
-  // row of the inverse; the padding column T of s1 holds 1 / L_qq.  The step
-  // count is bound by VALU instructions per wave (each costs 4 cycles) and
-  // LDS round trips, so a step issues all its reads at once, has no branch
-  // (a failed pivot is recorded and reported after the loop) and forms
-  // 1 / pivot from the broadcast pivot with v_rcp_f64 and two Newton steps.
-  double av[S], lv[S], xv[S];
-#pragma unroll
-  for (int i = 0; i < S; ++i) av[i] = a.A[tix(a, k, k, r0 + i, q)];
-  const double thr = (double)a.n * 2.220446049250313e-16 * (a.amp + delta);
-  double my_piv = 1.0;
-  bool bad = false;
-  for (int c = 0; c < T; ++c) {
-    double* col = colbuf[c & 1];
-    if (q == c) {
-#pragma unroll
-      for (int i = 0; i < S; ++i) col[r0 + i] = av[i];
-    }
-    __syncthreads();
-    double cv[S];
-#pragma unroll
-    for (int i = 0; i < S; ++i) cv[i] = col[r0 + i];
-    const double piv = col[c];
-    const double cq = col[q];
-    const double lim = (k * T + c) < a.n ? thr : 0.0;
-    bad |= !(piv > lim) || !(piv < INFINITY);
-    if ((k * T + c) < a.n) *pmin = fmin(*pmin, piv);
-    my_piv = q == c ? piv : my_piv;
-    double rp = __builtin_amdgcn_rcp(piv);
-    rp = fma(rp, fma(-piv, rp, 1.0), rp);
-    rp = fma(rp, fma(-piv, rp, 1.0), rp);
-    // columns q > c take the update on every row: the entries above the
-    // diagonal are never read, so they need no mask
-    const double cqs = q > c ? cq * rp : 0.0;
-#pragma unroll
-    for (int i = 0; i < S; ++i) av[i] = fma(-cv[i], cqs, av[i]);
+  for (int e = tt; e < T * T; e += NT) {
+    const int r = e >> 6, c = e & 63;
+    s1[r][c] = a.A[tix(a, k, k, r, c)];
   }
-  if (bad) return true;  // uniform: every thread saw the same pivots
-  // column q of L: A_rq / sqrt(pivot_q) below the diagonal
-  const double sq = sqrt(my_piv);
-  const double inv_sq = 1.0 / sq;
+  __syncthreads();
+  if (tt < 64) {
+    const int lane = tt, g = lane >> 4, c = lane & 15;
+    const double thr = (double)a.n * 2.220446049250313e-16 * (a.amp + delta);
+    bool bad = false;
+    double pm = INFINITY;
+#pragma unroll 1
+    for (int kb = 0; kb < 4 && !bad; ++kb) {
+      const int o = 16 * kb;
+      // the sub-block from its lower triangle (the upper one is stale)
+      double d[4];
 #pragma unroll
-  for (int i = 0; i < S; ++i) {
-    const int r = r0 + i;
-    lv[i] = r > q ? av[i] * inv_sq : (r == q ? sq : 0.0);
-  }
-  if (w == 0) s1[q][T] = inv_sq;  // 1 / L_qq for the inverse
+      for (int i = 0; i < 4; ++i) {
+        const int r = g + 4 * i;
+        d[i] = r >= c ? s1[o + r][o + c] : s1[o + c][o + r];
+      }
+      // The block stays exactly symmetric (loaded from one triangle, each
+      // update D_rc -= L_rp L_cp computed alike for (r, c) and (c, r)), so
+      // L_cp comes from row p (lanes of row group p%4) and L_rp from column p
+      // (lane p of the lane's row group); neither waits for the pivot.
+      double inv[16];
 #pragma unroll
-  for (int i = 0; i < S; ++i) xv[i] = (r0 + i == q) ? 1.0 : 0.0;
-  for (int r = 0; r < T; ++r) {
-    double* col = colbuf[r & 1];
-    double* xr = xbuf[r & 1];
-    if (q == r) {
+      for (int p = 0; p < 16; ++p) {
+        const double piv = readlane_d(d[p >> 2], 16 * (p & 3) + p);
+        const double dpc = __shfl(d[p >> 2], 16 * (p & 3) + c, 64);
+        double dcol[4];
 #pragma unroll
-      for (int i = 0; i < S; ++i) col[r0 + i] = lv[i];
+        for (int i = 0; i < 4; ++i) dcol[i] = __shfl(d[i], 16 * g + p, 64);
+        const int R = k * T + o + p;
+        bad |= !(piv > (R < a.n ? thr : 0.0)) || !(piv < INFINITY);
+        if (R < a.n) pm = fmin(pm, piv);
+        // sqrt(piv) and 1 / sqrt(piv): hardware reciprocal square root, two
+        // Goldschmidt steps, a Newton correction of each
+        double h = 0.5 * __builtin_amdgcn_rsq(piv), q = 2.0 * h * piv;
+        double e = fma(-h, q, 0.5);
+        q = fma(q, e, q);
+        h = fma(h, e, h);
+        e = fma(-h, q, 0.5);
+        q = fma(q, e, q);
+        h = fma(h, e, h);
+        const double sq = fma(fma(-q, q, piv), h, q);
+        double y = 2.0 * h;
+        y = fma(y, fma(-sq, y, 1.0), y);
+        inv[p] = y;
+        const double lc = c > p ? dpc * y : (c == p ? sq : 0.0);  // L_cp
+        const double w = c > p ? lc : 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = g + 4 * i;
+          const double lr = r > p ? dcol[i] * y : (r == p ? sq : 0.0);  // L_rp
+          d[i] = c == p ? lr : fma(-lr, w, d[i]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s1[o + g + 4 * i][o + c] = d[i];
+      // X = L_bb^-1, row by row: X_r = (e_r - sum_{m<r} L_rm X_m) / L_rr;
+      // X_rc comes from row group r%4, L_(g+4i) r from lane r of the row group
+      double x[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[i] = g + 4 * i == c ? 1.0 : 0.0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        double lrow[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lrow[i] = __shfl(d[i], 16 * g + r, 64);
+        const double xr = __shfl(x[r >> 2], 16 * (r & 3) + c, 64) * inv[r];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int rr = g + 4 * i;
+          x[i] = rr == r ? xr : (rr > r ? fma(-lrow[i], xr, x[i]) : x[i]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s0[o + g + 4 * i][o + c] = x[i];
+      wave_lds_sync();
+      // panel, then trailing update of the lower blocks
+      for (int ib = kb + 1; ib < 4; ++ib) {
+        const f64x4 lb = mm16_nt(s1, 16 * ib, o, s0, o, o, (f64x4){0.0, 0.0, 0.0, 0.0}, lane);
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s1[16 * ib + g + 4 * i][o + c] = lb[i];
+      }
+      wave_lds_sync();
+      for (int jb = kb + 1; jb < 4; ++jb) {
+        for (int ib = jb; ib < 4; ++ib) {
+          const f64x4 u = mm16_nt(s1, 16 * ib, o, s1, 16 * jb, o, (f64x4){0.0, 0.0, 0.0, 0.0}, lane);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            double& t = s1[16 * ib + g + 4 * i][16 * jb + c];
+            t -= u[i];
+          }
+        }
+      }
+      wave_lds_sync();
     }
-    if (r0 <= r && r < r0 + S) {
+    if (!bad) {
+      // X_ij = -X_ii sum_{m=j}^{i-1} L_im X_mj, block rows in order
+      for (int ib = 1; ib < 4; ++ib) {
+        for (int jb = 0; jb < ib; ++jb) {
+          f64x4 t = {0.0, 0.0, 0.0, 0.0};
+          for (int m = jb; m < ib; ++m) t = mm16_nn(s1, 16 * ib, 16 * m, s0, 16 * m, 16 * jb, t, lane);
+          const f64x4 xi = mm16_nr(s0, 16 * ib, 16 * ib, t, (f64x4){0.0, 0.0, 0.0, 0.0}, lane);
 #pragma unroll
-      for (int i = 0; i < S; ++i)
-        if (r0 + i == r) xr[q] = xv[i];
+          for (int i = 0; i < 4; ++i) s0[16 * ib + g + 4 * i][16 * jb + c] = -xi[i];
+        }
+        wave_lds_sync();
+      }
+      // zeros above the diagonal blocks
+      for (int ib = 0; ib < 4; ++ib)
+        for (int jb = ib + 1; jb < 4; ++jb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            s0[16 * ib + g + 4 * i][16 * jb + c] = 0.0;
+            s1[16 * ib + g + 4 * i][16 * jb + c] = 0.0;
+          }
     }
-    __syncthreads();
-    if (r0 + S - 1 >= r) {
-      double cv[S];
-#pragma unroll
-      for (int i = 0; i < S; ++i) cv[i] = col[r0 + i];
-      const double x = xr[q] * s1[r][T];
-      // L is zero above the diagonal, so rows before r are left unchanged
-#pragma unroll
-      for (int i = 0; i < S; ++i) xv[i] = (r0 + i == r) ? x : fma(-cv[i], x, xv[i]);
+    if (lane == 0) {
+      xbuf[0][0] = bad ? 1.0 : 0.0;
+      xbuf[0][1] = pm;
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int i = 0; i < S; ++i) {
-    s1[r0 + i][q] = lv[i];
-    s0[r0 + i][q] = xv[i];
-  }
+  const bool bad = xbuf[0][0] != 0.0;
+  const double pm = xbuf[0][1];
   __syncthreads();
+  if (bad) return true;
+  *pmin = fmin(*pmin, pm);
   return false;
 }
 
