@@ -505,16 +505,28 @@ __device__ void pack_elem16(const FitArgs& a, int64_t e) {
   else ((float*)a.Bpk)[e] = (float)v;
 }
 
-// BF16X3, 32x32x16 operand: fragment (J, t) at J(J+1) + t, t <= 2J+1; lane l
-// holds 8 values L^-1[32J + l%32][16t + 8(l/32) + e]; high parts first, then
-// the low parts (value - high) in a second array of the same shape.
+// BF16X3, 32x32x16 operand.  Column block J (32 columns of L^-T) has nonzero
+// k-steps t <= 2J+1 (16 observations each); it is stored with 4(J/2 + 1)
+// fragments, a whole number of 64-observation chunks, the extra ones zero:
+// block J starts at fragment 4m(m+1) (J = 2m) or 4(m+1)^2 (J = 2m+1).  Lane
+// l of fragment (J, t) holds 8 values L^-1[32J + l%32][16t + 8(l/32) + e];
+// high parts first, then the low parts (value - high) in a second array of
+// the same shape.
+__device__ __forceinline__ int64_t frag32_base(int J) {
+  const int64_t m = J >> 1;
+  return (J & 1) ? 4 * (m + 1) * (m + 1) : 4 * m * (m + 1);
+}
+
 __device__ void pack_elem32(const FitArgs& a, int64_t e, int64_t nfrag) {
   const int64_t f = e >> 6;
   const int l = (int)(e & 63);
-  int J = (int)((sqrt(4.0 * (double)f + 1.0) - 1.0) * 0.5);
-  while ((int64_t)(J + 1) * (J + 2) <= f) ++J;
-  while ((int64_t)J * (J + 1) > f) --J;
-  const int t = (int)(f - (int64_t)J * (J + 1));
+  // block pair m covers fragments [4m(m+1), 4(m+1)(m+2))
+  int64_t m = (int64_t)((sqrt((double)f + 1.0) - 1.0) * 0.5);
+  while (4 * (m + 1) * (m + 2) <= f) ++m;
+  while (4 * m * (m + 1) > f) --m;
+  const int64_t u = f - 4 * m * (m + 1);
+  const int J = (int)(2 * m + (u >= 4 * (m + 1) ? 1 : 0));
+  const int t = (int)(f - frag32_base(J));
   uint16_t hi[8], lo[8];
   for (int q = 0; q < 8; ++q) {
     const float v = (float)linv_at(a, 32 * J + (l & 31), 16 * t + 8 * (l >> 5) + q);
@@ -537,8 +549,8 @@ __device__ void pack_elem32(const FitArgs& a, int64_t e, int64_t nfrag) {
 
 __device__ __forceinline__ int64_t pack_count(const FitArgs& a, int64_t* nfrag) {
   if (a.prec == BO_BF16X3) {
-    const int64_t JB = a.n_pad / 32;
-    *nfrag = JB * (JB + 1);
+    const int64_t M = a.n_pad / 64;  // block pairs
+    *nfrag = 4 * M * (M + 1);
   } else {
     const int64_t JB = a.n_pad / 16;
     *nfrag = 2 * JB * (JB + 1);

@@ -1,7 +1,7 @@
 // Posterior of the BF16X3 precision mode (exhaustive prediction, Section
 // III-G) on the matrix cores.
 //
-// Persistent kernel: each workgroup of 8 waves loops over tiles of 64
+// Persistent kernel: each workgroup of 16 waves loops over tiles of 64
 // compacted candidates; the observation coordinates, their squared norms and
 // alpha are parked in LDS once.  For a tile the observations are streamed in
 // chunks of 64:
@@ -12,11 +12,14 @@
 //    high part and a bfloat16 remainder, written to LDS in the A-operand
 //    order of the 32x32x16 bfloat16 product (double-buffered: the next chunk
 //    is generated while the current one is consumed);
-//  - contraction: each wave owns up to four 32-column blocks of W = K* L^-T
-//    (blocks w, w+8, w+16, w+24) for all 64 candidates and accumulates
-//    hi*hi + hi*lo + lo*hi in FP32, skipping the all-zero tiles above the
-//    diagonal.  The L^-1 fragments of the next k-step are loaded as soon as
-//    the current ones have been consumed.
+//  - contraction: each wave owns up to two 32-column blocks of W = K* L^-T
+//    (blocks w and 31 - w, so every wave has the same number of k-steps at
+//    n_pad = 1024) for all 64 candidates and accumulates hi*hi + hi*lo +
+//    lo*hi in FP32.  The all-zero tiles above the diagonal are skipped: each
+//    block's fragments cover whole chunks, so the blocks a wave updates are
+//    decided once per chunk.  The L^-1 fragments of the next k-step are
+//    requested (buffer loads at scalar offsets) as soon as the current ones
+//    have been consumed.
 // The squared column sums are combined across waves in a fixed order,
 // var = amp - sum |W_c|^2 is clamped at zero, and the tile's mean-variance
 // partial goes to the tile's slot.
@@ -28,10 +31,12 @@ namespace bo {
 namespace {
 
 constexpr int kRows = 64;
-constexpr int kThreads = 512;
-constexpr int kWaves = kThreads / 64;
-constexpr int kQ = 32 / kWaves;  // column blocks per wave (n <= 1024)
+constexpr int kWaves = 16;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kQ = 32 / kWaves;     // column blocks per wave (n <= 1024)
+constexpr int kGen = 16 / kWaves;   // 16x16 generation blocks per wave and chunk
 constexpr int kChunk = 64;  // observations per LDS chunk (4 k-steps of 16)
+constexpr int kFragBytes = 64 * 16;  // one 32x32x16 operand fragment
 // row pitch of the observation coordinates in LDS: 17 floats, so that the 16
 // observations a quarter-wave reads in the distance products fall in
 // distinct banks (a pitch of 16 puts them in two)
@@ -44,6 +49,11 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
   const f32x2 v = {a, b};
   const bf16x2 r = __builtin_convertvector(v, bf16x2);
   return *reinterpret_cast<const uint32_t*>(&r);
+}
+
+__device__ __forceinline__ uint4 load_frag(__amdgpu_buffer_rsrc_t r, int lane_off, int off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, off, 0);
+  return make_uint4(v[0], v[1], v[2], v[3]);
 }
 
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) {
@@ -65,7 +75,7 @@ struct __align__(16) Smem {
   float xn[kMaxN];          // their squared norms
   double alpha[kMaxN];
   float sq[kWaves][kRows];
-  double mu[2][kRows];
+  double mu[kWaves / 4][kRows];
   double rsum[kThreads];
   int64_t rcnt[kThreads];
   int last;
@@ -100,18 +110,37 @@ __global__ __launch_bounds__(kThreads) void k_post_bf16x3(PostArgs p, int ntiles
     S.xn[i] = s;
   }
 
-  // generation role: row block rb (16 candidates), observation blocks ob0 and
-  // ob0 + 2 of each chunk; lane l works on candidate rb*16 + l%16 and the four
-  // observations 4(l/16) .. 4(l/16)+3 of a block
+  // generation role: row block rb (16 candidates), observation blocks
+  // ob0 + (kWaves / 4) j, j < kGen, of each chunk; lane l works on candidate
+  // rb*16 + l%16 and the four observations 4(l/16) .. 4(l/16)+3 of a block
   const int rb = w & 3, ob0 = w >> 2;
   const int lrow = rb * 16 + (lane & 15);
   const int g_rg = lrow >> 5;
   const int g_lane = (lrow & 31) + 32 * (lane >> 5);
   const int g_word = 2 * ((lane >> 4) & 1);  // 4-element half of the 16-byte slot
 
-  const uint4* Bhi = (const uint4*)p.Bpk;
-  const int64_t nfrag = (int64_t)JB * (JB + 1);
-  const uint4* Blo = Bhi + nfrag * 64;
+  // this wave's 32-column blocks of W in ascending order, w and 31 - w with
+  // 16 waves (w, 15 - w, 16 + w, 31 - w with 8): the same number of k-steps
+  // for every wave at n_pad = 1024; the first nact exist.  Block J's fragments
+  // start at frag32 base(J) and cover whole chunks (zero past k-step 2J+1),
+  // so the set of blocks a chunk updates changes only between chunks.
+  int Jq[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) Jq[q] = (q & 1) ? kWaves * (q + 1) - 1 - w : kWaves * q + w;
+  int nact = 0;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) nact += Jq[q] < JB ? 1 : 0;
+  const int M = p.n_pad / 64;
+  const int nfrag = 4 * M * (M + 1);
+  const __amdgpu_buffer_rsrc_t rB = buffer_of(p.Bpk, nfrag * 2 * kFragBytes);
+  const int lo_off = nfrag * kFragBytes;
+  int fb[kQ];  // byte offset of fragment 0 of each block (high parts)
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int m = Jq[q] >> 1;
+    fb[q] = ((Jq[q] & 1) ? 4 * (m + 1) * (m + 1) : 4 * m * (m + 1)) * kFragBytes;
+  }
+  const int loff = lane * 16;
 
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t row_base = (int64_t)tile * kRows;
@@ -177,17 +206,16 @@ __global__ __launch_bounds__(kThreads) void k_post_bf16x3(PostArgs p, int ntiles
         for (int i = 0; i < 16; ++i) acc[q][rg][i] = 0.f;
 
     __syncthreads();  // LDS tables ready; previous tile done with the buffers
-    finish(0, ob0, dist(0, ob0), S.buf[0]);
-    finish(0, ob0 + 2, dist(0, ob0 + 2), S.buf[0]);
-    // L^-1 fragments of k-step 0 (every index below is < nfrag)
+#pragma unroll
+    for (int j = 0; j < kGen; ++j) finish(0, ob0 + (kWaves / 4) * j, dist(0, ob0 + (kWaves / 4) * j), S.buf[0]);
+    // L^-1 fragments of k-step 0
     uint4 bh[kQ], bl[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-      const int J = w + kWaves * q;
-      const int Jc = J < JB ? J : 0;
-      const int64_t f = (int64_t)Jc * (Jc + 1);
-      bh[q] = Bhi[f * 64 + lane];
-      bl[q] = Blo[f * 64 + lane];
+      if (q < nact) {
+        bh[q] = load_frag(rB, loff, fb[q]);
+        bl[q] = load_frag(rB, loff, lo_off + fb[q]);
+      }
     }
     __syncthreads();
 
@@ -195,30 +223,34 @@ __global__ __launch_bounds__(kThreads) void k_post_bf16x3(PostArgs p, int ntiles
       const ChunkBuf& cur = S.buf[c & 1];
       ChunkBuf& nxt = S.buf[(c + 1) & 1];
       const bool more = c + 1 < NC;
+      // block q has nonzero k-steps in chunks 0 .. J/2; the blocks are in
+      // ascending order, so the active ones are those from q0 to nact - 1
+      bool act[kQ];
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) act[q] = q < nact && c <= (Jq[q] >> 1);
       f32x4 dd = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
       for (int s = 0; s < 4; ++s) {
         const int t = 4 * c + s;
-        const int tn = t + 1 < 2 * JB ? t + 1 : t;
-        // half an observation block of the next chunk per k-step
+        // a quarter (8 waves) or half (16 waves) of the next chunk's
+        // generation per k-step
         if (more) {
-          if (s == 0) dd = dist(c + 1, ob0);
-          if (s == 1) finish(c + 1, ob0, dd, nxt);
-          if (s == 2) dd = dist(c + 1, ob0 + 2);
-          if (s == 3) finish(c + 1, ob0 + 2, dd, nxt);
+          if (kGen == 2) {
+            if (s == 0) dd = dist(c + 1, ob0);
+            if (s == 1) finish(c + 1, ob0, dd, nxt);
+            if (s == 2) dd = dist(c + 1, ob0 + 2);
+            if (s == 3) finish(c + 1, ob0 + 2, dd, nxt);
+          } else {
+            if (s == 0) dd = dist(c + 1, ob0);
+            if (s == 2) finish(c + 1, ob0, dd, nxt);
+          }
         }
         const bf16x8 ah0 = as_bf16x8(cur.a[0][0][s][lane]);
         const bf16x8 ah1 = as_bf16x8(cur.a[0][1][s][lane]);
         const bf16x8 al0 = as_bf16x8(cur.a[1][0][s][lane]);
         const bf16x8 al1 = as_bf16x8(cur.a[1][1][s][lane]);
-        // three passes over the active column blocks (hi*hi, hi*lo, lo*hi)
-        // so that consecutive products write different accumulators
-        bool act[kQ];
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-          const int J = w + kWaves * q;
-          act[q] = J < JB && t <= 2 * J + 1;
-        }
+        // three passes over the active blocks (hi*hi, hi*lo, lo*hi) so that
+        // consecutive products write different accumulators
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
           if (act[q]) {
@@ -242,11 +274,13 @@ __global__ __launch_bounds__(kThreads) void k_post_bf16x3(PostArgs p, int ntiles
             acc[q][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al0, h, acc[q][0], 0, 0, 0);
             acc[q][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al1, h, acc[q][1], 0, 0, 0);
           }
-          const int J = w + kWaves * q;
-          const int Jc = J < JB ? J : 0;
-          const int64_t f = (int64_t)Jc * (Jc + 1) + tn;
-          bh[q] = Bhi[f * 64 + lane];
-          bl[q] = Blo[f * 64 + lane];
+          // the next k-step's fragments (past a block's end: the next
+          // block's, or zero past the buffer; never used)
+          if (act[q]) {
+            const int off = fb[q] + (t + 1) * kFragBytes;
+            bh[q] = load_frag(rB, loff, off);
+            bl[q] = load_frag(rB, loff, lo_off + off);
+          }
         }
       }
       __syncthreads();
@@ -287,7 +321,10 @@ __global__ __launch_bounds__(kThreads) void k_post_bf16x3(PostArgs p, int ntiles
         v = v > 0.0 ? v : 0.0;
         const float vf = (float)v;
         ((float*)p.var)[row] = vf;
-        ((float*)p.mu)[row] = (float)(mean_y + (S.mu[0][tid] + S.mu[1][tid]));
+        double m = 0.0;
+#pragma unroll
+        for (int i = 0; i < kWaves / 4; ++i) m += S.mu[i][tid];
+        ((float*)p.mu)[row] = (float)(mean_y + m);
         if (!(p.visited && p.visited[p.orig[row]])) {
           part = (double)vf;
           cnt = 1;

@@ -190,8 +190,8 @@ bo_status acq_params_check(const bo_acq_params* a, AcqArgs* out) {
 
 size_t bpk_bytes(int prec, int n_pad) {
   if (prec == BO_BF16X3) {
-    const size_t JB = n_pad / 32;
-    return JB * (JB + 1) * 64 * 16 * 2;
+    const size_t M = n_pad / 64;  // pairs of 32-column blocks, 4(m+1) fragments per block
+    return 4 * M * (M + 1) * 64 * 16 * 2;
   }
   const size_t JB = n_pad / 16;
   return 2 * JB * (JB + 1) * 64 * (prec == BO_FP64 ? 8 : 4);
