@@ -130,16 +130,20 @@ __device__ void post_tile(const BatchSession& S, int t, unsigned char* s_raw, do
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   double part = 0.0;
   int64_t cnt = 0;
-  if (!F32 && p.n_pad <= 16 * kRegJB) {
+  // FP64: the register-resident posterior; FP32: the operand parked in LDS
+  // (the register-resident FP32 form needs more registers than this kernel
+  // has; both FP32 forms compute the same values)
+  const bool reg = !F32 && p.n_pad <= 16 * kRegJB;
+  if (reg) {
     double* xs = (double*)s_raw;
     stage_obs(p, xs, xs + 16 * kRegJB * kObsPitch);
   }
   if (w < S.waves) {
     double* kt = (double*)s_raw + (size_t)w * S.rb * (p.n_pad >> 2) * 64;
     const int64_t row0 = (int64_t)t * S.rows + (int64_t)w * 16 * S.rb;
-    if (!F32 && p.n_pad <= 16 * kRegJB) {
+    if (reg) {
       // register-resident FP64 posterior, one block of 16 rows at a time,
-      // observations staged in LDS by post_tile
+      // observations staged in LDS above
       const double* xs = (const double*)s_raw;
       const double* as = xs + 16 * kRegJB * kObsPitch;
       for (int b = 0; b < S.rb; ++b) {
@@ -275,7 +279,7 @@ static_assert(kBatchLds >= kStageBytes, "staged observations");
 // within the kernel's LDS (each wave parks rb * n_pad * 16 operand entries).
 void tile_shape(int f32, int n_pad, int want_rb, int* rb, int* waves) {
   if (!f32 && n_pad <= 16 * kRegJB) {
-    // the register-resident FP64 posterior parks nothing in LDS
+    // the register-resident FP64 posterior parks no operand in LDS
     *rb = want_rb == 2 ? 2 : 1;
     *waves = kBWaves;
     return;

@@ -79,6 +79,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   if (last_block(&p.st->ticket_post, &s_last)) finish_lambda(p, gridDim.x, s_rsum, s_rcnt);
 }
 
+// FP32 (compensated) counterpart of k_post16r.  Up to 8 column blocks two
+// waves share a SIMD; above, the FP32 and FP64 sums and the FP64 operand
+// generation take one wave's whole register file (AGPRs included).
+template <int JB, int DM>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(JB > 8 ? 1 : 2, JB > 8 ? 1 : 2))) void
+k_post16r32(PostArgs p) {
+  __shared__ double s_wsum[4];
+  __shared__ int64_t s_wcnt[4];
+  __shared__ double s_rsum[256];
+  __shared__ int64_t s_rcnt[256];
+  __shared__ int s_last;
+  __shared__ double s_xo[16 * JB * kObsPitch];
+  __shared__ double s_alpha[16 * JB];
+  __shared__ float s_r[JB > 8 ? 4 * 4 * (JB / 2) * 64 : 1];  // residuals between the two passes
+  if (p.st->status != BO_OK) return;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * 16;
+  stage_obs(p, s_xo, s_alpha);
+  double part;
+  int64_t cnt;
+  post16_wave_reg32<JB, DM>(p, row0, s_xo, s_alpha, s_r + (JB > 8 ? w * 4 * (JB / 2) * 64 : 0), &part, &cnt);
+  if (l == 0) {
+    s_wsum[w] = part;
+    s_wcnt[w] = cnt;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    int64_t c = 0;
+    for (int i = 0; i < 4; ++i) {
+      s += s_wsum[i];
+      c += s_wcnt[i];
+    }
+    p.vslots[blockIdx.x].sum = s;
+    p.vslots[blockIdx.x].count = c;
+  }
+  if (last_block(&p.st->ticket_post, &s_last)) finish_lambda(p, gridDim.x, s_rsum, s_rcnt);
+}
+
+template <int JB>
+static void launch_post16r32(const PostArgs& a, int grid, hipStream_t st) {
+  if (a.d <= 8)
+    hipLaunchKernelGGL((k_post16r32<JB, 8>), dim3(grid), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_post16r32<JB, kMaxD>), dim3(grid), dim3(256), 0, st, a);
+}
+
 template <int JB>
 static void launch_post16r(const PostArgs& a, int grid, hipStream_t st) {
   if (a.d <= 8)
@@ -95,15 +142,16 @@ hipError_t launch_posterior(const DevPtrs& P, const Layout& Lo, const GpConst& g
                             const uint8_t* visited, const AcqArgs& acq, hipStream_t st) {
   const PostArgs a = make_post_args(P, Lo, g, n, n_valid, visited, acq);
   if (Lo.prec == BO_BF16X3) return launch_post_bf16x3(a, st);
-  if (Lo.prec == BO_FP64 && a.n_pad <= 16 * kRegJB) {
+  if (a.n_pad <= 16 * kRegJB) {
     int grid = (int)((n_valid + 63) / 64);
     grid = grid > 0 ? grid : 1;
-    switch (a.n_pad >> 4) {
-      case 4: launch_post16r<4>(a, grid, st); break;
-      case 8: launch_post16r<8>(a, grid, st); break;
-      case 12: launch_post16r<12>(a, grid, st); break;
-      case 16: launch_post16r<16>(a, grid, st); break;
-      default: return hipErrorInvalidValue;  // n_pad is a multiple of 64
+    const bool f64 = Lo.prec == BO_FP64;
+    switch (a.n_pad >> 4) {  // n_pad is a multiple of 64
+      case 4: f64 ? launch_post16r<4>(a, grid, st) : launch_post16r32<4>(a, grid, st); break;
+      case 8: f64 ? launch_post16r<8>(a, grid, st) : launch_post16r32<8>(a, grid, st); break;
+      case 12: f64 ? launch_post16r<12>(a, grid, st) : launch_post16r32<12>(a, grid, st); break;
+      case 16: f64 ? launch_post16r<16>(a, grid, st) : launch_post16r32<16>(a, grid, st); break;
+      default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
   }

@@ -113,6 +113,39 @@ __device__ inline void finish_lambda(const PostArgs& p, int nslots, double* s_su
 //
 // Writes mu and var (FP64 or FP32) of the rows below n_valid and returns, on
 // lane 0, the sum and count of the variances of the rows not yet evaluated.
+// Cross-covariance of the FP32-mode posterior (Section III-B), the same
+// arithmetic in every kernel that computes it, so that the single-session,
+// batched and served paths agree to the last bit: the squared distance as two
+// interleaved partial sums over the coordinates (zero past the d-th, which
+// adds nothing), then amp (1 + rho (1 + c2 rho)) exp(-rho), rho = c1 sqrt(s).
+struct KStar {
+  double amp, c1, c2;
+  __device__ KStar(const PostArgs& p) {
+    const bool nu5 = p.nu2 == 5;
+    amp = p.amp;
+    c1 = (nu5 ? 2.23606797749978969641 : 1.73205080756887729353) * p.inv_l;
+    c2 = nu5 ? 1.0 / 3.0 : 0.0;
+  }
+  __device__ double operator()(double s) const {
+    const double rho = c1 * sqrt(s);
+    return amp * (fma(rho, fma(c2, rho, 1.0), 1.0) * exp(-rho));
+  }
+};
+template <int DM>
+__device__ __forceinline__ double dist2_pairs(const double* xr, const double* xo) {
+  double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+  for (int j = 0; j < DM; j += 2) {
+    const double e0 = xr[j] - xo[j];
+    s0 = fma(e0, e0, s0);
+    if (j + 1 < DM) {
+      const double e1 = xr[j + 1] - xo[j + 1];
+      s1 = fma(e1, e1, s1);
+    }
+  }
+  return s0 + s1;
+}
+
 // Element (i, j) of L^-1 as a B operand, zero outside the lower triangle of
 // the current fit.
 __device__ __forceinline__ double linv_b(const PostArgs& p, int row, int col) {
@@ -156,21 +189,18 @@ __device__ void post16_wave(const PostArgs& p, int64_t row0, double* kt, double*
       }
     } else {
       // nearest observation of the row: the four lanes of a row scan disjoint
-      // observations, then compare (distance, index) pairs
+      // observations, then compare (distance, index) pairs.  The coordinates
+      // past the d-th are zero on both sides.
+      const KStar kstar(p);
+      double xo[kMaxD];
       double best = __builtin_inf();
       int bi = 0;
       for (int t = 0; t < nt4; ++t) {
         const int i = 4 * t + my_k;
         if (i < p.n) {
-          const double* xo = p.Xo64 + (size_t)i * kMaxD;
-          double s = 0.0;
 #pragma unroll
-          for (int j = 0; j < kMaxD; ++j) {
-            if (j < p.d) {
-              const double df = xr[j] - xo[j];
-              s += df * df;
-            }
-          }
+          for (int j = 0; j < kMaxD; ++j) xo[j] = j < p.d ? p.Xo64[(size_t)i * kMaxD + j] : 0.0;
+          const double s = dist2_pairs<kMaxD>(xr, xo);
           if (s < best) {
             best = s;
             bi = i;
@@ -187,7 +217,7 @@ __device__ void post16_wave(const PostArgs& p, int64_t row0, double* kt, double*
         }
       }
       // k*_p from the same distance the scan found, on every lane of the row
-      const double kp = p.amp * matern64(p.nu2, sqrt(best), p.inv_l);
+      const double kp = kstar(best);
       const double kpp = p.amp + p.st->jitter;
       const double c = kp / kpp;
       bs = p.amp - kp * c;
@@ -196,17 +226,10 @@ __device__ void post16_wave(const PostArgs& p, int64_t row0, double* kt, double*
         const int i = 4 * t + my_k;
         double rv = 0.0;
         if (i < p.n) {
-          const double* xo = p.Xo64 + (size_t)i * kMaxD;
-          double s = 0.0;
 #pragma unroll
-          for (int j = 0; j < kMaxD; ++j) {
-            if (j < p.d) {
-              const double df = xr[j] - xo[j];
-              s += df * df;
-            }
-          }
-          const double kv = p.amp * matern64(p.nu2, sqrt(s), p.inv_l);
-          mp += kv * p.alpha[i];
+          for (int j = 0; j < kMaxD; ++j) xo[j] = j < p.d ? p.Xo64[(size_t)i * kMaxD + j] : 0.0;
+          const double kv = kstar(dist2_pairs<kMaxD>(xr, xo));
+          mp = fma(kv, p.alpha[i], mp);
           rv = i == bi ? 0.0 : kv - c * krow[i];
         }
         ktb[t * 64 + l] = rv;
@@ -523,6 +546,298 @@ __device__ void post16_wave_reg(const PostArgs& p, int64_t row0, const double* x
         var[r] = v;
         if (!(visited && visited[orig[r]])) {
           part += v;
+          ++cnt;
+        }
+      }
+    }
+  }
+  part += __shfl_down(part, 16, 64);
+  part += __shfl_down(part, 32, 64);
+  cnt += __shfl_down(cnt, 16, 64);
+  cnt += __shfl_down(cnt, 32, 64);
+  *part_out = part;
+  *cnt_out = cnt;
+}
+
+// FP32 mode of post16_wave_reg (the compensated scheme of post16_wave<true>):
+// the wave first finds each row's nearest observation p (four lanes scan
+// disjoint observations, then compare distance and index), then in k-outer
+// order generates the FP64 k* of its A element, adds k*_i alpha_i to the FP64
+// mean and feeds the residual r_i = k*_i - (k*_p / K_pp) K_pi (zero at i = p),
+// rounded to FP32, to the FP32 16x16x4 products of every live column block.
+// A block's FP32 sums cover 4 k-steps (16 observations) and are then added
+// into its FP64 sums.  var = amp - k*_p^2 / K_pp - |L^-1 r|^2; where the
+// FP32 part is more than a quarter of what remains, the block of 16 rows is
+// redone with FP64 products against L^-1 itself (reg32_fallback).  With
+// more than 8 column blocks the FP32 and FP64 sums of all of them do not fit
+// in registers: the first half of the blocks (k-steps below their end) runs
+// first and leaves its FP32 residuals in rbuf (4 JB/2 x 64 floats per wave),
+// the second half reads them back instead of generating them again.  Same
+// outputs and slot partial as post16_wave<true>.
+template <int JB, int DM>
+struct Reg32 {
+  static constexpr int JH = JB > 8 ? JB / 2 : JB;  // blocks of the first pass
+  const PostArgs& p;
+  const double* xs;
+  const double* as;
+  float* rbuf;
+  int l, my_k, n, ld, bi;
+  double amp, c1, c2, c, mp;
+  double xr[DM];
+  gptr_t<const double> krow;
+  __amdgpu_buffer_rsrc_t rB;
+  double sq[4];
+
+  __device__ double dist2(int i) const { return dist2_pairs<DM>(xr, xs + i * kObsPitch); }
+  __device__ double kfun(double s) const {
+    const double rho = c1 * sqrt(s);
+    return amp * (fma(rho, fma(c2, rho, 1.0), 1.0) * exp(-rho));  // as KStar
+  }
+  // residual of k-step t, FP64; the mean takes k*_i alpha_i when `mean`
+  __device__ double resid(int t, bool mean) {
+    const int i = 4 * t + my_k;
+    const double kr = krow[i];
+    const double kv = i < n ? kfun(dist2(i)) : 0.0;
+    if (mean) mp = fma(kv, as[i], mp);
+    return (i < n && i != bi) ? kv - c * kr : 0.0;
+  }
+  __device__ float bval(int J, int t) const {
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_raw_buffer_load_b32(rB, l * 4, (2 * J * (J + 1) + t) * 64 * 4, 0));
+  }
+  // blocks JA .. JZ-1 over k-steps 0 .. 4 JZ - 1; the k-steps below TS = 4 JA
+  // come from rbuf, the others are generated (and stored in rbuf when STORE)
+  template <int JA, int JZ, int TS, bool STORE>
+  __device__ void pass() {
+    static_assert(TS == 4 * JA, "the k-steps before JA come from the first pass");
+    constexpr int NQ = JZ - JA;
+    f32x4 acc[NQ];
+    f64x4 a64[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      acc[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      a64[q] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    }
+    auto flush = [&](int q0) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        if (q >= q0) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) a64[q][i] += (double)acc[q][i];
+          acc[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        }
+      }
+    };
+    // k-steps before block JA's diagonal: every block of the range is live
+#pragma unroll 1
+    for (int g = 0; g < JA; ++g) {
+#pragma unroll 1
+      for (int tt = 0; tt < 4; ++tt) {
+        const int t = 4 * g + tt;
+        float bq[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) bq[q] = bval(JA + q, t);
+        const float rf = rbuf[t * 64 + l];  // stored by the first pass (TS = 4 JA)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rf, bq[q], acc[q], 0, 0, 0);
+      }
+      flush(0);
+    }
+    // then phase J0 = JA + q0: blocks q0 .. NQ-1
+#pragma unroll
+    for (int q0 = 0; q0 < NQ; ++q0) {
+#pragma unroll 1
+      for (int tt = 0; tt < 4; ++tt) {
+        const int t = 4 * (JA + q0) + tt;
+        float bq[NQ];
+#pragma unroll
+        for (int q = q0; q < NQ; ++q) bq[q] = bval(JA + q, t);
+        // k-steps from JA on are generated here (TS <= 4 JA)
+        const float rf = (float)resid(t, true);
+        if (STORE) rbuf[t * 64 + l] = rf;
+#pragma unroll
+        for (int q = q0; q < NQ; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rf, bq[q], acc[q], 0, 0, 0);
+      }
+      flush(q0);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sq[i] += a64[q][i] * a64[q][i];
+  }
+
+  // FP64 |L^-1 r|^2 contributions of blocks JA .. JZ-1 against L^-1 itself
+  // (rB64: buffer over L^-1, row stride ld), added to s64 (FP64 row order)
+  template <int JA, int JZ>
+  __device__ void fallback_pass(__amdgpu_buffer_rsrc_t rL, double* s64) {
+    constexpr int NQ = JZ - JA;
+    f64x4 acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = (f64x4){0.0, 0.0, 0.0, 0.0};
+    const int lrow = l & 15;
+#pragma unroll 1
+    for (int t = 0; t < 4 * JZ; ++t) {
+      const int i = 4 * t + my_k;
+      const double r = resid(t, false);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        // L^-1[16J + l%16][i], zero above the diagonal and past the fit
+        const int row = 16 * (JA + q) + lrow;
+        if (4 * t <= 16 * (JA + q) + 15) {
+          const double v = __builtin_bit_cast(
+              double, __builtin_amdgcn_raw_buffer_load_b64(rL, (lrow * ld + i) * 8, 16 * (JA + q) * ld * 8, 0));
+          const double bv = (i <= row && row < n) ? v : 0.0;
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(r, bv, acc[q], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) s64[i] += acc[q][i] * acc[q][i];
+  }
+
+  // |L^-1 r|^2 in FP64 against L^-1 itself, rows in the FP32 output order
+  __device__ void fallback() {
+    const __amdgpu_buffer_rsrc_t rL = buffer_of(uni(p.Linv), 16 * JB * ld * (int)sizeof(double));
+    double s64[4] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (JH < JB) {
+      fallback_pass<0, JH>(rL, s64);
+      fallback_pass<JH, JB>(rL, s64);
+    } else {
+      fallback_pass<0, JB>(rL, s64);
+    }
+    // FP64 product rows are l/16 + 4i; sum the columns, then move row q of
+    // the FP32 order (4 (l/16) + i) from register q/4 of the lanes l/16 = q%4
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double v = s64[i];
+      v += shfl_xor_d(v, 1);
+      v += shfl_xor_d(v, 2);
+      v += shfl_xor_d(v, 4);
+      v += shfl_xor_d(v, 8);
+      s64[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = 4 * my_k + i;
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double t = __shfl(s64[k], 16 * (q & 3), 64);
+        v = (q >> 2) == k ? t : v;
+      }
+      sq[i] = v;
+    }
+  }
+};
+
+// LDS floats of the residuals kept between the two passes, per wave.
+constexpr int kReg32Rbuf = 4 * (kRegJB / 2) * 64;
+
+template <int JB, int DM>
+__device__ void post16_wave_reg32(const PostArgs& p, int64_t row0, const double* xs, const double* as, float* rbuf,
+                                  double* part_out, int64_t* cnt_out) {
+  static_assert(JB >= 1 && JB <= kRegJB && DM <= kMaxD, "shape");
+  Reg32<JB, DM> R{p, xs, as, rbuf};
+  const int l = threadIdx.x & 63;
+  const int my_k = l >> 4;
+  R.l = l;
+  R.my_k = my_k;
+  row0 = uni(row0);
+  const int d = uni(p.d);
+  R.n = uni(p.n);
+  R.ld = uni(p.ld);
+  const bool nu5 = uni(p.nu2) == 5;
+  R.amp = uni(p.amp);
+  R.c1 = (nu5 ? 2.23606797749978969641 : 1.73205080756887729353) * uni(p.inv_l);
+  R.c2 = nu5 ? 1.0 / 3.0 : 0.0;
+  const int64_t n_valid = uni(p.n_valid), N_pad = uni(p.N_pad);
+  const auto X64 = gptr(uni(p.X64));
+  const auto orig = gptr(uni(p.orig));
+  const auto visited = gptr(uni(p.visited));
+  const auto mu = gptr((float*)uni(p.mu));
+  const auto var = gptr((float*)uni(p.var));
+  DevState* st = uni(p.st);
+  const double mean_y = st->mean_y, jitter = st->jitter;
+  const int64_t my_row = row0 + (l & 15);
+#pragma unroll
+  for (int j = 0; j < DM; ++j) {
+    const double v = X64[(int64_t)(j < d ? j : d - 1) * N_pad + my_row];
+    R.xr[j] = j < d ? v : 0.0;
+  }
+  // nearest observation of the row
+  double best = __builtin_inf();
+  int bi = 0;
+#pragma unroll 1
+  for (int t = 0; t < 4 * JB; ++t) {
+    const int i = 4 * t + my_k;
+    const double s = R.dist2(i);
+    const bool take = i < R.n && s < best;
+    best = take ? s : best;
+    bi = take ? i : bi;
+  }
+#pragma unroll
+  for (int m = 16; m <= 32; m <<= 1) {
+    const double ob = shfl_xor_d(best, m);
+    const int oi = __shfl_xor(bi, m, 64);
+    if (ob < best || (ob == best && oi < bi)) {
+      best = ob;
+      bi = oi;
+    }
+  }
+  R.bi = bi;
+  const double kp = R.kfun(best);
+  R.c = kp / (R.amp + jitter);
+  const double base = R.amp - kp * R.c;
+  R.krow = gptr((const double*)uni(p.K0)) + (int64_t)bi * R.ld;
+  // FP32 B operand of 16 JB column blocks: 2 JB (JB + 1) tiles of 64 lanes
+  R.rB = buffer_of(uni(p.Bpk), 2 * JB * (JB + 1) * 64 * (int)sizeof(float));
+  R.mp = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) R.sq[i] = 0.0;
+  constexpr int JH = Reg32<JB, DM>::JH;
+  if constexpr (JH < JB) {
+    R.template pass<0, JH, 0, true>();
+    R.template pass<JH, JB, 4 * JH, false>();
+  } else {
+    R.template pass<0, JB, 0, false>();
+  }
+  double mp = R.mp;
+  mp += shfl_xor_d(mp, 16);
+  mp += shfl_xor_d(mp, 32);
+  // output register i of lane l: row 4(l/16) + i, column l%16
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    double v = R.sq[i];
+    v += shfl_xor_d(v, 1);
+    v += shfl_xor_d(v, 2);
+    v += shfl_xor_d(v, 4);
+    v += shfl_xor_d(v, 8);
+    R.sq[i] = v;
+  }
+  // the row constant of output row 4 (l/16) + i sits on lane 4 (l/16) + i
+  double base_o[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) base_o[i] = __shfl(base, 4 * my_k + i, 64);
+  bool flag = false;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) flag |= row0 + 4 * my_k + i < n_valid && R.sq[i] > 4.0 * (base_o[i] - R.sq[i]);
+  if (__any(flag)) R.fallback();
+  double part = 0.0;
+  int64_t cnt = 0;
+  if (l < 16 && my_row < n_valid) mu[my_row] = (float)(mean_y + mp);
+  if ((l & 15) == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = row0 + 4 * my_k + i;
+      if (r < n_valid) {
+        double v = base_o[i] - R.sq[i];
+        v = v > 0.0 ? v : 0.0;
+        const float vf = (float)v;
+        var[r] = vf;
+        if (!(visited && visited[orig[r]])) {
+          part += (double)vf;
           ++cnt;
         }
       }
