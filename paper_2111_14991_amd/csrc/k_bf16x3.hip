@@ -1,7 +1,7 @@
 // Posterior of the BF16X3 precision mode (exhaustive prediction, Section
 // III-G) on the matrix cores.
 //
-// Persistent kernel: each workgroup of 16 waves loops over tiles of 64
+// Persistent kernel: each workgroup of 8 waves loops over tiles of 64
 // compacted candidates; the observation coordinates, their squared norms and
 // alpha are parked in LDS once.  For a tile the observations are streamed in
 // chunks of 64:
@@ -12,12 +12,12 @@
 //    high part and a bfloat16 remainder, written to LDS in the A-operand
 //    order of the 32x32x16 bfloat16 product (double-buffered: the next chunk
 //    is generated while the current one is consumed);
-//  - contraction: each wave owns up to two 32-column blocks of W = K* L^-T
-//    (blocks w and 31 - w, so every wave has the same number of k-steps at
-//    n_pad = 1024) for all 64 candidates and accumulates hi*hi + hi*lo +
-//    lo*hi in FP32.  The all-zero tiles above the diagonal are skipped: each
-//    block's fragments cover whole chunks, so the blocks a wave updates are
-//    decided once per chunk.  The L^-1 fragments of the next k-step are
+//  - contraction: each wave owns up to four 32-column blocks of W = K* L^-T
+//    (blocks w, 15 - w, 16 + w and 31 - w, so every wave has the same number
+//    of k-steps at n_pad = 1024) for all 64 candidates and accumulates
+//    hi*hi + hi*lo + lo*hi in FP32.  The all-zero tiles above the diagonal
+//    are skipped: each block's fragments cover whole chunks, so the blocks a
+//    wave updates are decided once per chunk.  The L^-1 fragments of the next k-step are
 //    requested (buffer loads at scalar offsets) as soon as the current ones
 //    have been consumed.
 // The squared column sums are combined across waves in a fixed order,
@@ -31,7 +31,7 @@ namespace bo {
 namespace {
 
 constexpr int kRows = 64;
-constexpr int kWaves = 16;
+constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kQ = 32 / kWaves;     // column blocks per wave (n <= 1024)
 constexpr int kGen = 16 / kWaves;   // 16x16 generation blocks per wave and chunk
