@@ -63,16 +63,34 @@ __device__ __forceinline__ void tri_decode(int t, int* i, int* j) {
   *j = t - r * (r + 1) / 2;
 }
 
+// Tile loads into LDS by a team of TT threads (tt < TT): every load of the
+// thread is issued before the first store, so their latencies overlap.
 __device__ __forceinline__ void load_tile(Tile& s, const double* M, const FitArgs& a, int ti, int tj, int tt) {
-  for (int e = tt; e < T * T; e += TT) {
-    const int r = e >> 6, c = e & 63;
-    s[r][c] = M[tix(a, ti, tj, r, c)];
+  constexpr int NQ = T * T / TT;
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = tt + q * TT;
+    v[q] = M[tix(a, ti, tj, e >> 6, e & 63)];
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = tt + q * TT;
+    s[e >> 6][e & 63] = v[q];
   }
 }
 
 __device__ __forceinline__ void load_dinv(Tile& s, const FitArgs& a, int k, int tt) {
   const double* D = a.Dinv + (size_t)k * T * T;
-  for (int e = tt; e < T * T; e += TT) s[e >> 6][e & 63] = D[e];
+  constexpr int NQ = T * T / TT;
+  double v[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) v[q] = D[tt + q * TT];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = tt + q * TT;
+    s[e >> 6][e & 63] = v[q];
+  }
 }
 
 // ---- phase 0: gather observations, validate, prior mean and incumbent ----
@@ -200,15 +218,17 @@ __device__ void op_gemm(double* C, const FitArgs& a, int ti, int tj, const Tile&
       acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[j], 0, 0, 0);
     }
   }
+  // all of C's current values are read before the first store (the stores
+  // could alias a later load as far as the compiler knows)
+  double base[4][4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const size_t ix = tix(a, ti, tj, 16 * w + kq + 4 * i, 16 * j + r);
-      const double base = accumulate ? C[ix] : 0.0;
-      C[ix] = base - sign * acc[j][i];
-    }
-  }
+    for (int i = 0; i < 4; ++i) base[j][i] = accumulate ? C[tix(a, ti, tj, 16 * w + kq + 4 * i, 16 * j + r)] : 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) C[tix(a, ti, tj, 16 * w + kq + 4 * i, 16 * j + r)] = base[j][i] - sign * acc[j][i];
 }
 
 // Wave-local LDS ordering: the wave's earlier LDS writes are seen by its
@@ -273,9 +293,19 @@ template <int NT>
 __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s1, double (*colbuf)[64],
                         double (*xbuf)[64], double* pmin) {
   const int tt = threadIdx.x;
-  for (int e = tt; e < T * T; e += NT) {
-    const int r = e >> 6, c = e & 63;
-    s1[r][c] = a.A[tix(a, k, k, r, c)];
+  {
+    constexpr int NQ = T * T / NT;
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tt + q * NT;
+      v[q] = a.A[tix(a, k, k, e >> 6, e & 63)];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tt + q * NT;
+      s1[e >> 6][e & 63] = v[q];
+    }
   }
   __syncthreads();
   if (tt < 64) {
@@ -469,12 +499,14 @@ __device__ void stepB_item(const FitArgs& a, int k, int t, Tile& s0, Tile& s1, i
 __device__ void alpha_z_row(const FitArgs& a, int i, double m, int lane) {
   double v = 0.0;
   if (i < a.n)
+#pragma unroll 4
     for (int j = lane; j <= i; j += 64) v += a.Linv[(size_t)i * a.ld + j] * (a.y[j] - m);
   for (int off = 32; off > 0; off >>= 1) v += shfl_xor_d(v, off);
   if (lane == 0) a.z[i] = v;
 }
 __device__ void alpha_a_row(const FitArgs& a, int i, int lane) {
   double v = 0.0;
+#pragma unroll 4
   for (int j = i + lane; j < a.n; j += 64) v += a.Linv[(size_t)j * a.ld + i] * a.z[j];
   for (int off = 32; off > 0; off >>= 1) v += shfl_xor_d(v, off);
   if (lane == 0) a.alpha[i] = i < a.n ? v : 0.0;
