@@ -101,30 +101,60 @@ __device__ void fit_gather(const FitArgs& a, double* s_red, int* s_pos, int* s_b
   if (t == 0) *s_bad = 0;
   __syncthreads();
   double yv = 0.0, ymin = INFINITY;
-  for (int i = t; i < a.n_pad; i += nt) {
-    int pos = 0;
-    double v = 0.0;
-    if (i < a.n) {
-      const int64_t idx = a.obs_idx[i];
-      v = a.y_in[i];
-      pos = (idx >= 0 && idx < a.N) ? a.inv_map[idx] : -1;
-      if (pos < 0 || !isfinite(v)) {
-        atomicExch(s_bad, 1);
-        pos = 0;
-      }
-      yv += v;
-      ymin = fmin(ymin, v);
+  // observations in groups of U per thread, every load of a group issued
+  // before the first store (the stores could alias later loads as far as
+  // the compiler knows, which would serialize the round trips)
+  constexpr int U = 4;
+  for (int i0 = t; i0 < a.n_pad; i0 += U * nt) {
+    int64_t idx[U];
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * nt;
+      idx[u] = i < a.n ? a.obs_idx[i] : -1;
+      v[u] = i < a.n ? a.y_in[i] : 0.0;
     }
-    s_pos[i] = pos;
-    a.y[i] = v;
+    int pos[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) pos[u] = (idx[u] >= 0 && idx[u] < a.N) ? a.inv_map[idx[u]] : -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * nt;
+      if (i >= a.n_pad) continue;
+      if (i < a.n) {
+        if (pos[u] < 0 || !isfinite(v[u])) {
+          atomicExch(s_bad, 1);
+          pos[u] = 0;
+        }
+        yv += v[u];
+        ymin = fmin(ymin, v[u]);
+      } else {
+        pos[u] = 0;
+      }
+      s_pos[i] = pos[u];
+      a.y[i] = v[u];
+    }
   }
   __syncthreads();
-  // coordinates: one (observation, dimension) pair per thread and round
-  for (int e = t; e < a.n_pad * kMaxD; e += nt) {
-    const int i = e / kMaxD, j = e % kMaxD;
-    const double x = (i < a.n && j < a.d) ? a.X64[(int64_t)j * a.N_pad + s_pos[i]] : 0.0;
-    a.Xo64[e] = x;
-    a.Xo32[e] = (float)x;
+  // coordinates: one (observation, dimension) pair per thread and round, in
+  // groups of 8 rounds
+  const int ne = a.n_pad * kMaxD;
+  for (int e0 = t; e0 < ne; e0 += 8 * nt) {
+    double x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * nt;
+      const int i = e / kMaxD, j = e % kMaxD;
+      x[u] = (e < ne && i < a.n && j < a.d) ? a.X64[(int64_t)j * a.N_pad + s_pos[i]] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * nt;
+      if (e < ne) {
+        a.Xo64[e] = x[u];
+        a.Xo32[e] = (float)x[u];
+      }
+    }
   }
   // fixed-order tree reductions of the sum and the minimum
   s_red[t] = yv;
@@ -160,10 +190,21 @@ __device__ void fit_gather(const FitArgs& a, double* s_red, int* s_pos, int* s_b
 // xs holds the coordinates of row block ti (rows 0..63) and column block tj
 // (rows 64..127) as [128][kMaxD + 1] doubles.
 __device__ void op_build(const FitArgs& a, int ti, int tj, double delta, double* xs, int tt) {
-  for (int e = tt; e < 128 * kMaxD; e += TT) {
-    const int r = e / kMaxD, j = e % kMaxD;
-    const int g = (r < 64 ? ti * T + r : tj * T + r - 64);
-    xs[r * (kMaxD + 1) + j] = a.Xo64[g * kMaxD + j];
+  {
+    constexpr int NQ = 128 * kMaxD / TT;
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tt + q * TT;
+      const int r = e / kMaxD, j = e % kMaxD;
+      const int g = (r < 64 ? ti * T + r : tj * T + r - 64);
+      v[q] = a.Xo64[g * kMaxD + j];
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = tt + q * TT;
+      xs[(e / kMaxD) * (kMaxD + 1) + e % kMaxD] = v[q];
+    }
   }
   __syncthreads();
   const int w = tt >> 6, c = tt & 63;
