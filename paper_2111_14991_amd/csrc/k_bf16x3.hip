@@ -229,7 +229,10 @@ __global__ __launch_bounds__(kThreads) void k_post_bf16x3(PostArgs p, int ntiles
 #pragma unroll
       for (int q = 0; q < kQ; ++q) act[q] = q < nact && c <= (Jq[q] >> 1);
       f32x4 dd = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
+      // the chunk's four k-steps unrolled: a step's A fragments can be read
+      // while the previous step's products run, and the generation pieces
+      // are placed at compile time
+#pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int t = 4 * c + s;
         // a quarter (8 waves) or half (16 waves) of the next chunk's
