@@ -79,27 +79,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   if (last_block(&p.st->ticket_post, &s_last)) finish_lambda(p, gridDim.x, s_rsum, s_rcnt);
 }
 
-// FP32 (compensated) counterpart of k_post16r.  Up to 8 column blocks two
-// waves share a SIMD; above, the FP32 and FP64 sums and the FP64 operand
-// generation take one wave's whole register file (AGPRs included).
+// FP32 (compensated) counterpart of k_post16r.  The residuals kept between
+// the passes and the last workgroup's reduction scratch share one LDS array
+// (the reduction runs after the workgroup's posterior), which keeps the
+// workgroup within 80 KB: two per CU.
 template <int JB, int DM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(JB > 8 ? 1 : 2, JB > 8 ? 1 : 2))) void
-k_post16r32(PostArgs p) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_post16r32(PostArgs p) {
+  constexpr int kStored = reg32_stored_steps(JB) * 64;  // residual floats per wave
+  constexpr int kRed = 256 * (sizeof(double) + sizeof(int64_t)) / sizeof(float);
+  constexpr int kR = 4 * kStored > kRed ? 4 * kStored : kRed;
   __shared__ double s_wsum[4];
   __shared__ int64_t s_wcnt[4];
-  __shared__ double s_rsum[256];
-  __shared__ int64_t s_rcnt[256];
+  __shared__ __align__(16) float s_r[kR];
   __shared__ int s_last;
   __shared__ double s_xo[16 * JB * kObsPitch];
   __shared__ double s_alpha[16 * JB];
-  __shared__ float s_r[JB > 8 ? 4 * 4 * (JB / 2) * 64 : 1];  // residuals between the two passes
   if (p.st->status != BO_OK) return;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * 16;
   stage_obs(p, s_xo, s_alpha);
   double part;
   int64_t cnt;
-  post16_wave_reg32<JB, DM>(p, row0, s_xo, s_alpha, s_r + (JB > 8 ? w * 4 * (JB / 2) * 64 : 0), &part, &cnt);
+  post16_wave_reg32<JB, DM>(p, row0, s_xo, s_alpha, s_r + w * kStored, &part, &cnt);
   if (l == 0) {
     s_wsum[w] = part;
     s_wcnt[w] = cnt;
@@ -115,7 +116,8 @@ k_post16r32(PostArgs p) {
     p.vslots[blockIdx.x].sum = s;
     p.vslots[blockIdx.x].count = c;
   }
-  if (last_block(&p.st->ticket_post, &s_last)) finish_lambda(p, gridDim.x, s_rsum, s_rcnt);
+  if (last_block(&p.st->ticket_post, &s_last))
+    finish_lambda(p, gridDim.x, (double*)s_r, (int64_t*)(s_r + 256 * sizeof(double) / sizeof(float)));
 }
 
 template <int JB>

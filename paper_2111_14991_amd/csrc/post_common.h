@@ -568,15 +568,16 @@ __device__ void post16_wave_reg(const PostArgs& p, int64_t row0, const double* x
 // A block's FP32 sums cover 4 k-steps (16 observations) and are then added
 // into its FP64 sums.  var = amp - k*_p^2 / K_pp - |L^-1 r|^2; where the
 // FP32 part is more than a quarter of what remains, the block of 16 rows is
-// redone with FP64 products against L^-1 itself (reg32_fallback).  With
-// more than 8 column blocks the FP32 and FP64 sums of all of them do not fit
-// in registers: the first half of the blocks (k-steps below their end) runs
-// first and leaves its FP32 residuals in rbuf (4 JB/2 x 64 floats per wave),
-// the second half reads them back instead of generating them again.  Same
+// redone with FP64 products against L^-1 itself (fallback).  With more than
+// 8 column blocks the FP32 and FP64 sums of all of them do not fit in
+// registers: the blocks run in two or three passes; each pass generates the
+// k-steps from its first block's diagonal on and leaves their FP32 residuals
+// in rbuf (reg32_stored_steps(JB) x 64 floats per wave), the later passes
+// read the earlier k-steps back instead of generating them again.  Same
 // outputs and slot partial as post16_wave<true>.
 template <int JB, int DM>
 struct Reg32 {
-  static constexpr int JH = JB > 8 ? JB / 2 : JB;  // blocks of the first pass
+  static constexpr int JH = JB > 8 ? JB / 2 : JB;  // split of the FP64 fallback
   const PostArgs& p;
   const double* xs;
   const double* as;
@@ -664,6 +665,10 @@ struct Reg32 {
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) sq[i] += a64[q][i] * a64[q][i];
+    // the squares are summed here, not after the later passes: otherwise
+    // the compiler keeps this pass's FP64 sums alive through them
+#pragma unroll
+    for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(sq[i]));
   }
 
   // FP64 |L^-1 r|^2 contributions of blocks JA .. JZ-1 against L^-1 itself
@@ -732,8 +737,10 @@ struct Reg32 {
   }
 };
 
-// LDS floats of the residuals kept between the two passes, per wave.
-constexpr int kReg32Rbuf = 4 * (kRegJB / 2) * 64;
+// k-steps whose FP32 residuals are kept for the later passes (those below the
+// last pass's first block), and the LDS floats they take per wave.
+constexpr int reg32_stored_steps(int JB) { return JB > 12 ? 40 : (JB > 8 ? 2 * JB : 0); }
+constexpr int kReg32Rbuf = reg32_stored_steps(kRegJB) * 64;
 
 template <int JB, int DM>
 __device__ void post16_wave_reg32(const PostArgs& p, int64_t row0, const double* xs, const double* as, float* rbuf,
@@ -796,10 +803,15 @@ __device__ void post16_wave_reg32(const PostArgs& p, int64_t row0, const double*
   R.mp = 0.0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) R.sq[i] = 0.0;
-  constexpr int JH = Reg32<JB, DM>::JH;
-  if constexpr (JH < JB) {
-    R.template pass<0, JH, 0, true>();
-    R.template pass<JH, JB, 4 * JH, false>();
+  // column blocks in passes of at most 6: their FP32 and FP64 sums fit in
+  // registers beside the generation at two waves per SIMD
+  if constexpr (JB > 12) {
+    R.template pass<0, 5, 0, true>();
+    R.template pass<5, 10, 20, true>();
+    R.template pass<10, JB, 40, false>();
+  } else if constexpr (JB > 8) {
+    R.template pass<0, JB / 2, 0, true>();
+    R.template pass<JB / 2, JB, 2 * JB, false>();
   } else {
     R.template pass<0, JB, 0, false>();
   }
