@@ -124,6 +124,24 @@ __device__ bool last_of(uint32_t* t, uint32_t total, int* s_flag) {
   return last;
 }
 
+// rb blocks of 16 rows from row0 with the register-resident FP64 posterior of
+// n_pad = 16 JB, a function of its own per shape so that each gets its own
+// register allocation
+template <int JB>
+__device__ __attribute__((noinline)) void reg_rows(const PostArgs& p, int64_t row0, int rb, const double* xs,
+                                                   double* part, int64_t* cnt) {
+  const double* as = xs + 16 * kRegJB * kObsPitch;
+  const bool small_d = uni(p.d) <= 8;
+  for (int b = 0; b < rb; ++b) {
+    double pb;
+    int64_t cb;
+    if (small_d) post16_wave_reg<JB, 8>(p, row0 + 16 * b, xs, as, &pb, &cb);
+    else post16_wave_reg<JB, kMaxD>(p, row0 + 16 * b, xs, as, &pb, &cb);
+    *part += pb;
+    *cnt += cb;
+  }
+}
+
 template <bool F32>
 __device__ void post_tile(const BatchSession& S, int t, unsigned char* s_raw, double* s_wsum, int64_t* s_wcnt) {
   const PostArgs& p = S.post;
@@ -145,13 +163,11 @@ __device__ void post_tile(const BatchSession& S, int t, unsigned char* s_raw, do
       // register-resident FP64 posterior, one block of 16 rows at a time,
       // observations staged in LDS above
       const double* xs = (const double*)s_raw;
-      const double* as = xs + 16 * kRegJB * kObsPitch;
-      for (int b = 0; b < S.rb; ++b) {
-        double pb;
-        int64_t cb;
-        post16_wave_reg_any(p, row0 + 16 * b, xs, as, &pb, &cb);
-        part += pb;
-        cnt += cb;
+      switch (p.n_pad >> 4) {  // a multiple of 4
+        case 4: reg_rows<4>(p, row0, S.rb, xs, &part, &cnt); break;
+        case 8: reg_rows<8>(p, row0, S.rb, xs, &part, &cnt); break;
+        case 12: reg_rows<12>(p, row0, S.rb, xs, &part, &cnt); break;
+        default: reg_rows<16>(p, row0, S.rb, xs, &part, &cnt); break;
       }
     } else if (S.rb == 2) {
       post16_wave<F32, 2>(p, row0, kt, &part, &cnt);
