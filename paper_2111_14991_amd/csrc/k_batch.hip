@@ -142,16 +142,32 @@ __device__ __attribute__((noinline)) void reg_rows(const PostArgs& p, int64_t ro
   }
 }
 
+// Same for the register-resident FP32 (compensated) posterior; rbuf: this
+// wave's kReg32Rbuf floats of LDS.
+template <int JB>
+__device__ __attribute__((noinline)) void reg32_rows(const PostArgs& p, int64_t row0, int rb, const double* xs,
+                                                     float* rbuf, double* part, int64_t* cnt) {
+  const double* as = xs + 16 * kRegJB * kObsPitch;
+  const bool small_d = uni(p.d) <= 8;
+  for (int b = 0; b < rb; ++b) {
+    double pb;
+    int64_t cb;
+    if (small_d) post16_wave_reg32<JB, 8>(p, row0 + 16 * b, xs, as, rbuf, &pb, &cb);
+    else post16_wave_reg32<JB, kMaxD>(p, row0 + 16 * b, xs, as, rbuf, &pb, &cb);
+    *part += pb;
+    *cnt += cb;
+  }
+}
+
 template <bool F32>
 __device__ void post_tile(const BatchSession& S, int t, unsigned char* s_raw, double* s_wsum, int64_t* s_wcnt) {
   const PostArgs& p = S.post;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   double part = 0.0;
   int64_t cnt = 0;
-  // FP64: the register-resident posterior; FP32: the operand parked in LDS
-  // (the register-resident FP32 form needs more registers than this kernel
-  // has; both FP32 forms compute the same values)
-  const bool reg = !F32 && p.n_pad <= 16 * kRegJB;
+  // the register-resident posterior (observations staged in LDS, then the
+  // FP32 mode's kept residuals, kReg32Rbuf floats per wave)
+  const bool reg = p.n_pad <= 16 * kRegJB;
   if (reg) {
     double* xs = (double*)s_raw;
     stage_obs(p, xs, xs + 16 * kRegJB * kObsPitch);
@@ -163,11 +179,21 @@ __device__ void post_tile(const BatchSession& S, int t, unsigned char* s_raw, do
       // register-resident FP64 posterior, one block of 16 rows at a time,
       // observations staged in LDS above
       const double* xs = (const double*)s_raw;
-      switch (p.n_pad >> 4) {  // a multiple of 4
-        case 4: reg_rows<4>(p, row0, S.rb, xs, &part, &cnt); break;
-        case 8: reg_rows<8>(p, row0, S.rb, xs, &part, &cnt); break;
-        case 12: reg_rows<12>(p, row0, S.rb, xs, &part, &cnt); break;
-        default: reg_rows<16>(p, row0, S.rb, xs, &part, &cnt); break;
+      float* rbuf = (float*)(s_raw + kStageBytes) + (size_t)w * kReg32Rbuf;
+      if (F32) {
+        switch (p.n_pad >> 4) {  // a multiple of 4
+          case 4: reg32_rows<4>(p, row0, S.rb, xs, rbuf, &part, &cnt); break;
+          case 8: reg32_rows<8>(p, row0, S.rb, xs, rbuf, &part, &cnt); break;
+          case 12: reg32_rows<12>(p, row0, S.rb, xs, rbuf, &part, &cnt); break;
+          default: reg32_rows<16>(p, row0, S.rb, xs, rbuf, &part, &cnt); break;
+        }
+      } else {
+        switch (p.n_pad >> 4) {
+          case 4: reg_rows<4>(p, row0, S.rb, xs, &part, &cnt); break;
+          case 8: reg_rows<8>(p, row0, S.rb, xs, &part, &cnt); break;
+          case 12: reg_rows<12>(p, row0, S.rb, xs, &part, &cnt); break;
+          default: reg_rows<16>(p, row0, S.rb, xs, &part, &cnt); break;
+        }
       }
     } else if (S.rb == 2) {
       post16_wave<F32, 2>(p, row0, kt, &part, &cnt);
@@ -289,13 +315,13 @@ __global__ void k_batch_clear(BatchSync* sync, int cap, BatchCtl* ctl) {
 
 constexpr size_t kBatchLds = kSmallLdsBytes;
 static_assert(kBatchLds >= 2 * kBThreads * sizeof(double), "finish_lambda scratch");
-static_assert(kBatchLds >= kStageBytes, "staged observations");
+static_assert(kBatchLds >= kStageBytes + kBWaves * kReg32Rbuf * sizeof(float), "staged observations and residuals");
 
 // Posterior tile shape of one session: row blocks per wave and active waves,
 // within the kernel's LDS (each wave parks rb * n_pad * 16 operand entries).
 void tile_shape(int f32, int n_pad, int want_rb, int* rb, int* waves) {
-  if (!f32 && n_pad <= 16 * kRegJB) {
-    // the register-resident FP64 posterior parks no operand in LDS
+  if (n_pad <= 16 * kRegJB) {
+    // the register-resident posterior parks no operand in LDS
     *rb = want_rb == 2 ? 2 : 1;
     *waves = kBWaves;
     return;
