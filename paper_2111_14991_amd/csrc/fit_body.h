@@ -16,6 +16,7 @@
 // included.  n > 256: one launch per A_k / B_k with one team per tile; the
 // host retries the jitter schedule after a pivot failure.
 #pragma once
+#include <type_traits>
 #include "bo_internal.h"
 #include "bo_device.h"
 
@@ -280,6 +281,15 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Lane N of each row of 16 lanes broadcast to the whole row (DPP
+// row_newbcast, a VALU move; N is a compile-time constant).
+template <int N>
+__device__ __forceinline__ double row_bcast_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + N, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + N, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
@@ -321,8 +331,9 @@ __device__ __forceinline__ f64x4 mm16_nr(const Tile& A, int ra, int ca, const f6
 // single wave, blocked in 16 x 16 sub-blocks (kb = 0..3):
 //  - the diagonal sub-block is held in registers (lane l: column l%16, rows
 //    l/16 + 4i) and factored column by column, the values each step needs
-//    passed between lanes by permutes; its inverse follows by forward
-//    substitution on the identity, row by row;
+//    passed between lanes (within a row of 16 lanes by DPP broadcasts,
+//    across rows by permutes); its inverse follows by forward substitution
+//    on the identity, row by row;
 //  - the panel L_ib = A_ib L_bb^-T and the trailing update
 //    A_ij -= L_ib L_jb^T are 16x16x16 FP64 matrix-core products;
 //  - the off-diagonal inverse blocks X_ij = -X_ii sum_m L_im X_mj, i > j.
@@ -369,13 +380,13 @@ __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s
       // L_cp comes from row p (lanes of row group p%4) and L_rp from column p
       // (lane p of the lane's row group); neither waits for the pivot.
       double inv[16];
-#pragma unroll
-      for (int p = 0; p < 16; ++p) {
+      auto step = [&](auto pc) {
+        constexpr int p = decltype(pc)::value;
         const double piv = readlane_d(d[p >> 2], 16 * (p & 3) + p);
         const double dpc = __shfl(d[p >> 2], 16 * (p & 3) + c, 64);
         double dcol[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dcol[i] = __shfl(d[i], 16 * g + p, 64);
+        for (int i = 0; i < 4; ++i) dcol[i] = row_bcast_d<p>(d[i]);
         const int R = k * T + o + p;
         bad |= !(piv > (R < a.n ? thr : 0.0)) || !(piv < INFINITY);
         if (R < a.n) pm = fmin(pm, piv);
@@ -392,15 +403,32 @@ __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s
         double y = 2.0 * h;
         y = fma(y, fma(-sq, y, 1.0), y);
         inv[p] = y;
-        const double lc = c > p ? dpc * y : (c == p ? sq : 0.0);  // L_cp
-        const double w = c > p ? lc : 0.0;
+        const double prod = dpc * y;
+        const double w = c > p ? prod : 0.0;  // L_cp where the column is updated
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int r = g + 4 * i;
-          const double lr = r > p ? dcol[i] * y : (r == p ? sq : 0.0);  // L_rp
+          const double pr = dcol[i] * y;
+          const double lr = r > p ? pr : (r == p ? sq : 0.0);  // L_rp
           d[i] = c == p ? lr : fma(-lr, w, d[i]);
         }
-      }
+      };
+      step(std::integral_constant<int, 0>());
+      step(std::integral_constant<int, 1>());
+      step(std::integral_constant<int, 2>());
+      step(std::integral_constant<int, 3>());
+      step(std::integral_constant<int, 4>());
+      step(std::integral_constant<int, 5>());
+      step(std::integral_constant<int, 6>());
+      step(std::integral_constant<int, 7>());
+      step(std::integral_constant<int, 8>());
+      step(std::integral_constant<int, 9>());
+      step(std::integral_constant<int, 10>());
+      step(std::integral_constant<int, 11>());
+      step(std::integral_constant<int, 12>());
+      step(std::integral_constant<int, 13>());
+      step(std::integral_constant<int, 14>());
+      step(std::integral_constant<int, 15>());
 #pragma unroll
       for (int i = 0; i < 4; ++i) s1[o + g + 4 * i][o + c] = d[i];
       // X = L_bb^-1, row by row: X_r = (e_r - sum_{m<r} L_rm X_m) / L_rr;
@@ -408,18 +436,34 @@ __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s
       double x[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) x[i] = g + 4 * i == c ? 1.0 : 0.0;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
+      auto istep = [&](auto rc) {
+        constexpr int r = decltype(rc)::value;
         double lrow[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) lrow[i] = __shfl(d[i], 16 * g + r, 64);
+        for (int i = 0; i < 4; ++i) lrow[i] = row_bcast_d<r>(d[i]);
         const double xr = __shfl(x[r >> 2], 16 * (r & 3) + c, 64) * inv[r];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int rr = g + 4 * i;
           x[i] = rr == r ? xr : (rr > r ? fma(-lrow[i], xr, x[i]) : x[i]);
         }
-      }
+      };
+      istep(std::integral_constant<int, 0>());
+      istep(std::integral_constant<int, 1>());
+      istep(std::integral_constant<int, 2>());
+      istep(std::integral_constant<int, 3>());
+      istep(std::integral_constant<int, 4>());
+      istep(std::integral_constant<int, 5>());
+      istep(std::integral_constant<int, 6>());
+      istep(std::integral_constant<int, 7>());
+      istep(std::integral_constant<int, 8>());
+      istep(std::integral_constant<int, 9>());
+      istep(std::integral_constant<int, 10>());
+      istep(std::integral_constant<int, 11>());
+      istep(std::integral_constant<int, 12>());
+      istep(std::integral_constant<int, 13>());
+      istep(std::integral_constant<int, 14>());
+      istep(std::integral_constant<int, 15>());
 #pragma unroll
       for (int i = 0; i < 4; ++i) s0[o + g + 4 * i][o + c] = x[i];
       wave_lds_sync();
