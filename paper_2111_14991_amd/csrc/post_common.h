@@ -863,23 +863,6 @@ __device__ void post16_wave_reg32(const PostArgs& p, int64_t row0, const double*
   *cnt_out = cnt;
 }
 
-// Calls post16_wave_reg with the shape of p (n_pad <= 16 kRegJB).
-__device__ inline void post16_wave_reg_any(const PostArgs& p, int64_t row0, const double* xs, const double* as,
-                                           double* part_out, int64_t* cnt_out) {
-  const int jb = uni(p.n_pad) >> 4;
-  const bool small_d = uni(p.d) <= 8;
-#define BO_REG_CASE(JBV)                                                          \
-  case JBV:                                                                       \
-    if (small_d) post16_wave_reg<JBV, 8>(p, row0, xs, as, part_out, cnt_out);     \
-    else post16_wave_reg<JBV, kMaxD>(p, row0, xs, as, part_out, cnt_out);         \
-    break;
-  switch (jb) {
-    BO_REG_CASE(4) BO_REG_CASE(8) BO_REG_CASE(12) BO_REG_CASE(16)
-    default: break;
-  }
-#undef BO_REG_CASE
-}
-
 // LDS bytes of stage_obs for n_pad <= 16 kRegJB.
 constexpr size_t kStageBytes = (size_t)16 * kRegJB * (kObsPitch + 1) * sizeof(double);
 
