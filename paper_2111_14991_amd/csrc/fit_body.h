@@ -273,14 +273,6 @@ __device__ void op_gemm(double* C, const FitArgs& a, int ti, int tj, const Tile&
     for (int i = 0; i < 4; ++i) C[tix(a, ti, tj, 16 * w + kq + 4 * i, 16 * j + r)] = base[j][i] - sign * acc[j][i];
 }
 
-// Wave-local LDS ordering: the wave's earlier LDS writes are seen by its
-// later reads (the other waves of the workgroup are not involved).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Lane N of each row of 16 lanes broadcast to the whole row (DPP
 // row_newbcast, a VALU move; N is a compile-time constant).
 template <int N>
@@ -360,14 +352,15 @@ __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s
     }
   }
   __syncthreads();
-  if (tt < 64) {
-    const int lane = tt, g = lane >> 4, c = lane & 15;
-    const double thr = (double)a.n * 2.220446049250313e-16 * (a.amp + delta);
-    bool bad = false;
-    double pm = INFINITY;
+  static_assert(NT >= 6 * 64, "one wave per trailing product");
+  const int wv = uni(tt >> 6), lane = tt & 63, g = lane >> 4, c = lane & 15;
+  const double thr = (double)a.n * 2.220446049250313e-16 * (a.amp + delta);
+  bool bad = false;  // wave 0
+  double pm = INFINITY;
 #pragma unroll 1
-    for (int kb = 0; kb < 4 && !bad; ++kb) {
-      const int o = 16 * kb;
+  for (int kb = 0; kb < 4; ++kb) {
+    const int o = 16 * kb;
+    if (wv == 0) {
       // the sub-block from its lower triangle (the upper one is stale)
       double d[4];
 #pragma unroll
@@ -466,59 +459,74 @@ __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s
       istep(std::integral_constant<int, 15>());
 #pragma unroll
       for (int i = 0; i < 4; ++i) s0[o + g + 4 * i][o + c] = x[i];
-      wave_lds_sync();
-      // panel, then trailing update of the lower blocks
-      for (int ib = kb + 1; ib < 4; ++ib) {
+    }
+    __syncthreads();
+    // panel: wave w forms L_ib,kb = A_ib,kb X_kb,kb^T for ib = kb + 1 + w
+    {
+      const int ib = kb + 1 + wv;
+      if (ib < 4) {
         const f64x4 lb = mm16_nt(s1, 16 * ib, o, s0, o, o, (f64x4){0.0, 0.0, 0.0, 0.0}, lane);
-        wave_lds_sync();
 #pragma unroll
         for (int i = 0; i < 4; ++i) s1[16 * ib + g + 4 * i][o + c] = lb[i];
       }
-      wave_lds_sync();
-      for (int jb = kb + 1; jb < 4; ++jb) {
-        for (int ib = jb; ib < 4; ++ib) {
-          const f64x4 u = mm16_nt(s1, 16 * ib, o, s1, 16 * jb, o, (f64x4){0.0, 0.0, 0.0, 0.0}, lane);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            double& t = s1[16 * ib + g + 4 * i][16 * jb + c];
-            t -= u[i];
+    }
+    __syncthreads();
+    // trailing update: wave w takes the w-th block (ib, jb), kb < jb <= ib
+    {
+      const int m = 3 - kb;  // blocks after kb
+      if (wv < m * (m + 1) / 2) {
+        int jb = 0, ib = 0, u = wv;
+        for (int q = 0; q < m; ++q) {
+          if (u < m - q) {
+            jb = kb + 1 + q;
+            ib = jb + u;
+            break;
           }
+          u -= m - q;
+        }
+        const f64x4 upd = mm16_nt(s1, 16 * ib, o, s1, 16 * jb, o, (f64x4){0.0, 0.0, 0.0, 0.0}, lane);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          double& t = s1[16 * ib + g + 4 * i][16 * jb + c];
+          t -= upd[i];
         }
       }
-      wave_lds_sync();
     }
-    if (!bad) {
-      // X_ij = -X_ii sum_{m=j}^{i-1} L_im X_mj, block rows in order
-      for (int ib = 1; ib < 4; ++ib) {
-        for (int jb = 0; jb < ib; ++jb) {
-          f64x4 t = {0.0, 0.0, 0.0, 0.0};
-          for (int m = jb; m < ib; ++m) t = mm16_nn(s1, 16 * ib, 16 * m, s0, 16 * m, 16 * jb, t, lane);
-          const f64x4 xi = mm16_nr(s0, 16 * ib, 16 * ib, t, (f64x4){0.0, 0.0, 0.0, 0.0}, lane);
+    __syncthreads();
+  }
+  // X_ij = -X_ii sum_{m=j}^{i-1} L_im X_mj, block row by block row; wave w
+  // takes block column jb = w
+  for (int ib = 1; ib < 4; ++ib) {
+    const int jb = wv;
+    if (jb < ib) {
+      f64x4 t = {0.0, 0.0, 0.0, 0.0};
+      for (int m = jb; m < ib; ++m) t = mm16_nn(s1, 16 * ib, 16 * m, s0, 16 * m, 16 * jb, t, lane);
+      const f64x4 xi = mm16_nr(s0, 16 * ib, 16 * ib, t, (f64x4){0.0, 0.0, 0.0, 0.0}, lane);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) s0[16 * ib + g + 4 * i][16 * jb + c] = -xi[i];
-        }
-        wave_lds_sync();
-      }
-      // zeros above the diagonal blocks
-      for (int ib = 0; ib < 4; ++ib)
-        for (int jb = ib + 1; jb < 4; ++jb)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            s0[16 * ib + g + 4 * i][16 * jb + c] = 0.0;
-            s1[16 * ib + g + 4 * i][16 * jb + c] = 0.0;
-          }
+      for (int i = 0; i < 4; ++i) s0[16 * ib + g + 4 * i][16 * jb + c] = -xi[i];
     }
-    if (lane == 0) {
-      xbuf[0][0] = bad ? 1.0 : 0.0;
-      xbuf[0][1] = pm;
+    __syncthreads();
+  }
+  // zeros above the diagonal blocks: wave w < 6 clears the w-th upper block
+  if (wv < 6) {
+    const int ib = wv < 3 ? 0 : (wv < 5 ? 1 : 2);
+    const int jb = wv < 3 ? wv + 1 : (wv < 5 ? wv - 1 : 3);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      s0[16 * ib + g + 4 * i][16 * jb + c] = 0.0;
+      s1[16 * ib + g + 4 * i][16 * jb + c] = 0.0;
     }
   }
+  if (tt == 0) {
+    xbuf[0][0] = bad ? 1.0 : 0.0;
+    xbuf[0][1] = pm;
+  }
   __syncthreads();
-  const bool bad = xbuf[0][0] != 0.0;
-  const double pm = xbuf[0][1];
+  const bool fail = xbuf[0][0] != 0.0;
+  const double pmv = xbuf[0][1];
   __syncthreads();
-  if (bad) return true;
-  *pmin = fmin(*pmin, pm);
+  if (fail) return true;
+  *pmin = fmin(*pmin, pmv);
   return false;
 }
 
