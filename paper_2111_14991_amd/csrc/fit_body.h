@@ -277,9 +277,26 @@ __device__ void op_gemm(double* C, const FitArgs& a, int ti, int tj, const Tile&
 // row_newbcast, a VALU move; N is a compile-time constant).
 template <int N>
 __device__ __forceinline__ double row_bcast_d(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + N, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + N, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + N, 0xf, 0xf, false);
+}
+
+// Row Q of v (lanes 16Q .. 16Q+15) copied to all four rows: the lane swaps
+// of gfx950 (upper half with lower half, then odd rows with even rows), VALU
+// moves only.
+template <int Q>
+__device__ __forceinline__ double row_copy_d(double v) {
+  const unsigned wd[2] = {(unsigned)__double2loint(v), (unsigned)__double2hiint(v)};
+  unsigned r[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    // {lower half twice, upper half twice}
+    const auto a = __builtin_amdgcn_permlane32_swap(wd[h], wd[h], false, false);
+    const unsigned half = Q < 2 ? a[0] : a[1];
+    // {even row of each pair everywhere, odd row everywhere}
+    const auto b = __builtin_amdgcn_permlane16_swap(half, half, false, false);
+    r[h] = (Q & 1) ? b[1] : b[0];
+  }
+  return __hiloint2double((int)r[1], (int)r[0]);
 }
 
 __device__ __forceinline__ double readlane_d(double v, int lane) {
@@ -368,43 +385,30 @@ __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s
         const int r = g + 4 * i;
         d[i] = r >= c ? s1[o + r][o + c] : s1[o + c][o + r];
       }
-      // The block stays exactly symmetric (loaded from one triangle, each
-      // update D_rc -= L_rp L_cp computed alike for (r, c) and (c, r)), so
-      // L_cp comes from row p (lanes of row group p%4) and L_rp from column p
-      // (lane p of the lane's row group); neither waits for the pivot.
-      double inv[16];
+      // Elimination without square roots: step p subtracts D_rp D_pc / D_pp
+      // from every column c > p (rows at or above p become rounding noise
+      // above the diagonal, cleared below) and keeps column p, so that
+      // column p ends as L_rp sqrt(D_pp) with D_pp the p-th pivot.  D_rp
+      // comes from lane p of the lane's row, D_pc from row p of the lane's
+      // column; only a reciprocal lies on the chain from pivot to pivot.
+      double pcol = 1.0;  // the pivot of the lane's column
       auto step = [&](auto pc) {
         constexpr int p = decltype(pc)::value;
         const double piv = readlane_d(d[p >> 2], 16 * (p & 3) + p);
-        const double dpc = __shfl(d[p >> 2], 16 * (p & 3) + c, 64);
-        double dcol[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) dcol[i] = row_bcast_d<p>(d[i]);
+        const double dpc = row_copy_d<p & 3>(d[p >> 2]);
         const int R = k * T + o + p;
         bad |= !(piv > (R < a.n ? thr : 0.0)) || !(piv < INFINITY);
         if (R < a.n) pm = fmin(pm, piv);
-        // sqrt(piv) and 1 / sqrt(piv): hardware reciprocal square root, two
-        // Goldschmidt steps, a Newton correction of each
-        double h = 0.5 * __builtin_amdgcn_rsq(piv), q = 2.0 * h * piv;
-        double e = fma(-h, q, 0.5);
-        q = fma(q, e, q);
-        h = fma(h, e, h);
-        e = fma(-h, q, 0.5);
-        q = fma(q, e, q);
-        h = fma(h, e, h);
-        const double sq = fma(fma(-q, q, piv), h, q);
-        double y = 2.0 * h;
-        y = fma(y, fma(-sq, y, 1.0), y);
-        inv[p] = y;
-        const double prod = dpc * y;
-        const double w = c > p ? prod : 0.0;  // L_cp where the column is updated
+        double rp = __builtin_amdgcn_rcp(piv);
+        double e = fma(-piv, rp, 1.0);
+        rp = fma(rp, e, rp);
+        e = fma(-piv, rp, 1.0);
+        rp = fma(rp, e, rp);
+        const double nw = c > p ? -(dpc * rp) : 0.0;
+        pcol = c == p ? piv : pcol;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int r = g + 4 * i;
-          const double pr = dcol[i] * y;
-          const double lr = r > p ? pr : (r == p ? sq : 0.0);  // L_rp
-          d[i] = c == p ? lr : fma(-lr, w, d[i]);
-        }
+        for (int i = 0; i < 4; ++i)
+          if (4 * i + 3 >= p) d[i] = fma(row_bcast_d<p>(d[i]), nw, d[i]);
       };
       step(std::integral_constant<int, 0>());
       step(std::integral_constant<int, 1>());
@@ -422,24 +426,44 @@ __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s
       step(std::integral_constant<int, 13>());
       step(std::integral_constant<int, 14>());
       step(std::integral_constant<int, 15>());
+      // sqrt(pivot) and 1 / sqrt(pivot) of the lane's column: hardware
+      // reciprocal square root, two Goldschmidt steps, a Newton correction
+      // of each
+      double h = 0.5 * __builtin_amdgcn_rsq(pcol), q = 2.0 * h * pcol;
+      double e = fma(-h, q, 0.5);
+      q = fma(q, e, q);
+      h = fma(h, e, h);
+      e = fma(-h, q, 0.5);
+      q = fma(q, e, q);
+      h = fma(h, e, h);
+      const double sq = fma(fma(-q, q, pcol), h, q);
+      double y = 2.0 * h;
+      y = fma(y, fma(-sq, y, 1.0), y);
+      // L_rc = D_rc / sqrt(D_cc) below the diagonal, sqrt(D_cc) on it; the
+      // unit factor U = L diag(L)^-1 (diagonal left at zero: never used)
+      double u[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = g + 4 * i;
+        const double lv = d[i] * y;
+        d[i] = r > c ? lv : (r == c ? sq : 0.0);
+        u[i] = r > c ? lv * y : 0.0;
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i) s1[o + g + 4 * i][o + c] = d[i];
-      // X = L_bb^-1, row by row: X_r = (e_r - sum_{m<r} L_rm X_m) / L_rr;
-      // X_rc comes from row group r%4, L_(g+4i) r from lane r of the row group
-      double x[4];
+      // Z = U^-1 by rows: once row r of Z is final, every row m takes away
+      // U_mr Z_r (rows at or above r meet a zero of U); then
+      // L^-1 = diag(1 / L_rr) Z.  Row r of Z comes from row r%4, register
+      // r/4; U_mr from lane r of the lane's row.
+      double z[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) x[i] = g + 4 * i == c ? 1.0 : 0.0;
+      for (int i = 0; i < 4; ++i) z[i] = g + 4 * i == c ? 1.0 : 0.0;
       auto istep = [&](auto rc) {
         constexpr int r = decltype(rc)::value;
-        double lrow[4];
+        const double zr = row_copy_d<r & 3>(z[r >> 2]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) lrow[i] = row_bcast_d<r>(d[i]);
-        const double xr = __shfl(x[r >> 2], 16 * (r & 3) + c, 64) * inv[r];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int rr = g + 4 * i;
-          x[i] = rr == r ? xr : (rr > r ? fma(-lrow[i], xr, x[i]) : x[i]);
-        }
+        for (int i = 0; i < 4; ++i)
+          if (4 * i + 3 > r) z[i] = fma(-row_bcast_d<r>(u[i]), zr, z[i]);
       };
       istep(std::integral_constant<int, 0>());
       istep(std::integral_constant<int, 1>());
@@ -456,9 +480,8 @@ __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s
       istep(std::integral_constant<int, 12>());
       istep(std::integral_constant<int, 13>());
       istep(std::integral_constant<int, 14>());
-      istep(std::integral_constant<int, 15>());
 #pragma unroll
-      for (int i = 0; i < 4; ++i) s0[o + g + 4 * i][o + c] = x[i];
+      for (int i = 0; i < 4; ++i) s0[o + g + 4 * i][o + c] = z[i] * __shfl(y, g + 4 * i, 64);
     }
     __syncthreads();
     // panel: wave w forms L_ib,kb = A_ib,kb X_kb,kb^T for ib = kb + 1 + w
