@@ -35,18 +35,22 @@ def _report(name, err):
     return q[2]
 
 
-@pytest.mark.parametrize("n", [1, 37, 100, 300, 1000])
-def test_bf16x3_mid_size_parity(bo, n):
-    s = W.make_session(20 + n, (6, 6, 6, 6, 6), n, invalid_frac=0.3)
-    S = bo.Session(s.N, s.d, s.n, "bf16x3")
+def bf16x3_parity(bo, s, gp=None, acq_mode=1):
+    """One BF16X3 step against the oracle: mean and variance of every
+    candidate, the mean variance, lambda and the chosen indices within TOL_B.
+    Contextual mode takes the step as the first after the initial sample."""
+    n = s.n
+    gpp = gp or bo.GpParams()
+    ogp = oracle.GP(gpp.nu2, gpp.lengthscale, gpp.amp, gpp.noise, gpp.jitter_tries)
+    S = bo.Session(s.N, s.d, s.n, "bf16x3", gp=gpp)
     S.set_grid(s.levels, None, s.invalid)
     S.fit(s.obs_idx, s.y)
     mu_s = float(np.mean(s.y[:s.n_init]))
-    r = S.acquire(s.visited(), bo.AcqParams(mode=1, mu_s=mu_s))
+    r = S.acquire(s.visited(), bo.AcqParams(mode=acq_mode, mu_s=mu_s))
     mu, var, vm = S.posterior(s.visited())
     mu, var = mu.cpu().numpy(), var.cpu().numpy()
     X = oracle.normalize_grid(s.levels)
-    ref = oracle.step(X, s.invalid, s.visited(), s.obs_idx, s.y, acq=oracle.Acq(mode=1, mu_s=mu_s),
+    ref = oracle.step(X, s.invalid, s.visited(), s.obs_idx, s.y, ogp, oracle.Acq(mode=acq_mode, mu_s=mu_s),
                       want_posterior=True)
     mask = (s.invalid | s.visited()).astype(bool)
     keep = ~mask
@@ -66,6 +70,11 @@ def test_bf16x3_mid_size_parity(bo, n):
         _report(f"n={n} {name}", e)
         assert PR.index_ok(int(r.idx[q]), int(ref.idx[q]), A_r, q, mask, TOL_B, scales[q]), (q, r.idx, ref.idx)
     S.close()
+
+
+@pytest.mark.parametrize("n", [1, 37, 100, 300, 1000])
+def test_bf16x3_mid_size_parity(bo, n):
+    bf16x3_parity(bo, W.make_session(20 + n, (6, 6, 6, 6, 6), n, invalid_frac=0.3))
 
 
 def test_bf16x3_full_size_sampled(bo):
