@@ -36,6 +36,9 @@ MULTI = {
           "autotuned tile shapes",
     "c5": "1024 live sessions (sizes as in c4, 10-200 initial observations), Poisson arrivals of step requests, "
           "rank-1 append per request, 64 GB HBM admission budget, continuous batching over 3 launch streams",
+    "loop": "tuning runs in simulation mode on the 102,060-point 8-parameter grid (25% restricted, 5% failing "
+            "when run): maximin LHS initial sample of 20, 200 further evaluations, contextual variance, "
+            "advanced multi acquisition (Table I settings)",
 }
 
 WORKLOADS = {
@@ -323,6 +326,63 @@ def bench_serving(args, torch, bo, W) -> int:
     return 0
 
 
+def bench_loop(args, torch, bo, W) -> int:
+    """Whole tuning runs: `--steps` runs after `--warmup` runs, each a fresh
+    draw of the initial design on one simulated problem.  value = BO
+    iterations (evaluations chosen by a step) per second."""
+    from paper_2111_14991_amd import bo_loop as BL
+    precision = args.precision or "fp32"
+    sim = W.make_simulation(0, (12, 7, 5, 3, 3, 3, 3, 3), invalid_frac=0.25, hidden_frac=0.05)
+    f_opt = float(np.nanmin(sim.table))
+    ev = lambda i: float(sim.table[i])
+    params = BL.LoopParams()
+    S = bo.Session(sim.N, sim.d, params.budget, precision, device="cuda:0")
+    S.set_grid(sim.levels, None, sim.invalid)
+
+    def one(r):
+        return BL.TuningRun(bo, S, sim.levels, sim.invalid, ev, W.loop_draws(1000 + r, 20, sim.d), params).run()
+
+    for r in range(args.warmup):
+        one(r)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    traces = [one(args.warmup + r) for r in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = sum(sum(1 for c in t.chooser if c >= 0) for t in traces)
+    steps = sum(t.steps for t in traces)
+    maes = [BL.mean_abs_error(t.best_after(), f_opt) for t in traces]
+    cpu = None
+    if not args.no_cpu:
+        # one whole oracle run (about 15 s on 8 cores) on the first timed run's problem and draws
+        from oracle import loop as OL
+        t1 = time.perf_counter()
+        tr = OL.run(sim.levels, sim.invalid, ev, W.loop_draws(1000 + args.warmup, 20, sim.d), OL.LoopParams())
+        t_cpu = time.perf_counter() - t1
+        n_it = sum(1 for c in tr.chooser if c >= 0)
+        import oracle
+        cpu = {"value": n_it / t_cpu, "unit": "BO iterations/s", "cores": oracle.threads(), "kind": "oracle",
+               "sample": f"one oracle tuning run of {len(tr.evaluated)} evaluations ({n_it} chosen by a step) "
+                         "on the problem and draws of the first timed run"}
+    line = {
+        "metric": "BO iterations/s in simulation-mode tuning runs",
+        "value": iters / dt, "unit": "BO iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / max(iters, 1) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "fp64", "fp32": "fp32"}.get(precision, precision), "data": "synthetic",
+        "config": {"workload": "loop: " + MULTI["loop"], "configurations": sim.N, "runs": args.steps,
+                   "precision": precision, "strategy": params.strategy},
+        "ms_per_run": dt / args.steps * 1e3, "gpu_steps": steps,
+        "mae": {"mean": float(np.mean(maes)), "std": float(np.std(maes)), "f_opt": f_opt},
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    S.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -359,6 +419,8 @@ def main() -> int:
         return bench_batched(args, torch, bo, W)
     if args.workload == "c5":
         return bench_serving(args, torch, bo, W)
+    if args.workload == "loop":
+        return bench_loop(args, torch, bo, W)
     wl = dict(WORKLOADS[args.workload])
     if args.precision and args.precision != wl["precision"]:
         wl.update(precision=args.precision, dtype={"bf16x3": "bf16"}.get(args.precision, args.precision),

@@ -34,7 +34,7 @@ __all__ = [
     "Landscape", "Session", "grid_size", "decode_levels", "make_landscape",
     "product_restriction", "quantile_restrictions", "make_session",
     "config_c1", "config_c2", "config_c3", "config_c4", "config_c5_population",
-    "tiny_session",
+    "tiny_session", "Simulation", "make_simulation", "LoopDraws", "loop_draws",
 ]
 
 
@@ -276,3 +276,68 @@ def tiny_session(seed: int, levels: Sequence[int] = (4, 3, 5), n_obs: int = 5,
                  invalid_frac: float = 0.2) -> Session:
     """A few-dozen-point space for brute-force checks."""
     return make_session(seed, levels, n_obs, invalid_frac=invalid_frac, name="tiny")
+
+
+# ---------------------------------------------------------------------------
+# Tuning runs in simulation mode (the outer loop around the step)
+
+
+@dataclass
+class Simulation:
+    """A cached tuning problem: the run time of every configuration drawn once
+    (a measurement cache replayed by the loop), restrictions known before
+    tuning (`invalid`, pruned from the search), and configurations that only
+    fail when run (`hidden`, unknown to the optimizer until evaluated).
+    `table` is NaN where a configuration is invalid or fails."""
+    levels: tuple
+    invalid: np.ndarray
+    hidden: np.ndarray
+    table: np.ndarray
+    seed: int = 0
+
+    @property
+    def N(self) -> int:
+        return int(self.invalid.shape[0])
+
+    @property
+    def d(self) -> int:
+        return len(self.levels)
+
+
+def make_simulation(seed: int, levels: Sequence[int], invalid_frac: float = 0.2,
+                    hidden_frac: float = 0.05) -> Simulation:
+    """Landscape, restrictions, failing configurations (each restriction-valid
+    configuration with probability `hidden_frac`), then one noisy measurement
+    per configuration, drawn in that order from PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    levels = tuple(int(k) for k in levels)
+    total = grid_size(levels)
+    land = make_landscape(rng, levels)
+    g = np.arange(total, dtype=np.int64)
+    invalid = quantile_restrictions(rng, levels, g, invalid_frac)
+    hidden = ((rng.random(total) < hidden_frac) & (invalid == 0)).astype(np.uint8)
+    f = land.value(g) * np.exp(0.02 * rng.standard_normal(total))
+    table = np.where((invalid == 0) & (hidden == 0), f, np.nan)
+    return Simulation(levels, invalid, hidden, table, seed)
+
+
+@dataclass
+class LoopDraws:
+    """The random numbers one tuning run consumes.  `perm[m, j]` is a
+    permutation of the `samples` strata of parameter j in Latin hypercube
+    design m and `off[m, j]` the positions within the strata (uniform on
+    [0, 1)); `repl` is a stream of uniforms for the random replacements of
+    invalid initial samples."""
+    perm: np.ndarray
+    off: np.ndarray
+    repl: np.ndarray
+
+
+def loop_draws(seed: int, samples: int, d: int, designs: int = 32, repl: int = 4096) -> LoopDraws:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    perm = np.empty((designs, d, samples), dtype=np.int64)
+    for m in range(designs):
+        for j in range(d):
+            perm[m, j] = rng.permutation(samples)
+    off = rng.random((designs, d, samples))
+    return LoopDraws(perm, off, rng.random(repl))
