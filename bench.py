@@ -364,6 +364,23 @@ def bench_loop(args, torch, bo, W) -> int:
         cpu = {"value": n_it / t_cpu, "unit": "BO iterations/s", "cores": oracle.threads(), "kind": "oracle",
                "sample": f"one oracle tuning run of {len(tr.evaluated)} evaluations ({n_it} chosen by a step) "
                          "on the problem and draws of the first timed run"}
+    # strategies compared on the three Table II-sized problems (Section IV-A's MAE and MDF)
+    strategies = BL.STRATEGIES
+    probs = W.table2_problems(0)
+    runs = 5
+    mm = np.zeros((len(strategies), len(probs)))
+    for k, pr in enumerate(probs):
+        Sk = bo.Session(pr.N, pr.d, params.budget, precision, device="cuda:0")
+        Sk.set_grid(pr.levels, None, pr.invalid)
+        opt = float(np.nanmin(pr.table))
+        evk = lambda i, t=pr.table: float(t[i])
+        for si, st in enumerate(strategies):
+            e = [BL.mean_abs_error(BL.TuningRun(bo, Sk, pr.levels, pr.invalid, evk, W.loop_draws(2000 + r, 20, pr.d),
+                                                BL.LoopParams(strategy=st)).run().best_after(), opt)
+                 for r in range(runs)]
+            mm[si, k] = np.mean(e)
+        Sk.close()
+    mdf, mdf_sd = BL.mean_deviation_factor(mm)
     line = {
         "metric": "BO iterations/s in simulation-mode tuning runs",
         "value": iters / dt, "unit": "BO iterations/s",
@@ -375,6 +392,11 @@ def bench_loop(args, torch, bo, W) -> int:
                    "precision": precision, "strategy": params.strategy},
         "ms_per_run": dt / args.steps * 1e3, "gpu_steps": steps,
         "mae": {"mean": float(np.mean(maes)), "std": float(np.std(maes)), "f_opt": f_opt},
+        "strategy_comparison": {
+            "problems": [f"{p.N} configurations, {int((p.invalid == 0).sum())} unrestricted, "
+                         f"{int(p.hidden.sum())} failing" for p in probs],
+            "runs": runs, "mean_mae": {st: mm[i].tolist() for i, st in enumerate(strategies)},
+            "mdf": {st: [float(mdf[i]), float(mdf_sd[i])] for i, st in enumerate(strategies)}},
         "roofline": None,
         "cpu_baseline": cpu,
     }

@@ -187,6 +187,23 @@ def mae(best_after: Sequence[float], f_opt: float) -> float:
     return tot / 10.0
 
 
+def mdf(mean_mae):
+    """Mean deviation factor (Section IV-A) from mean_mae[s][k], the mean MAE
+    of strategy s on problem k over its runs: each problem's values divided
+    by their mean over the strategies, then the mean and the standard
+    deviation over the problems.  Returns [(mdf, std)] per strategy."""
+    S, K = len(mean_mae), len(mean_mae[0])
+    out = []
+    for s in range(S):
+        f = []
+        for k in range(K):
+            col = sum(mean_mae[t][k] for t in range(S)) / S
+            f.append(mean_mae[s][k] / col)
+        m = sum(f) / K
+        out.append((m, math.sqrt(sum((v - m) ** 2 for v in f) / K)))
+    return out
+
+
 def incumbents(values: Sequence[float]) -> List[float]:
     out, b = [], math.inf
     for v in values:

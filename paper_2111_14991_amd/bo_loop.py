@@ -33,8 +33,11 @@ decides which configuration to evaluate next and keeps the run's books.
   discounted observation score is sum_i o_i g^(t-i) over a function's own
   observations, a failed configuration counted as the median of the valid
   observations at that time.
-- Metrics (Section IV-A): the incumbent after every evaluation and the mean
-  absolute error against the optimum over evaluations 40, 60, ..., 220.
+- Metrics (Section IV-A): the incumbent after every evaluation, the mean
+  absolute error against the optimum over evaluations 40, 60, ..., 220, and
+  the mean deviation factor of strategies over several problems (each
+  problem's mean errors divided by their mean over the strategies, averaged
+  over the problems).
 """
 from __future__ import annotations
 
@@ -77,6 +80,15 @@ class RunTrace:
 def mean_abs_error(best_after: np.ndarray, f_opt: float) -> float:
     marks = np.minimum(20 * np.arange(2, 12), best_after.shape[0]) - 1
     return float(np.mean(np.abs(best_after[marks] - f_opt)))
+
+
+def mean_deviation_factor(mean_mae: np.ndarray):
+    """MDF of Section IV-A: mean_mae[s, k] (strategy s, problem k) divided by
+    the problem's mean over the strategies, then mean and standard deviation
+    over the problems, per strategy."""
+    m = np.asarray(mean_mae, dtype=np.float64)
+    f = m / m.mean(axis=0, keepdims=True)
+    return f.mean(axis=1), f.std(axis=1)
 
 
 def maximin_lhs(levels: Sequence[int], perm: np.ndarray, off: np.ndarray) -> np.ndarray:

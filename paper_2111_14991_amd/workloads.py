@@ -34,7 +34,7 @@ __all__ = [
     "Landscape", "Session", "grid_size", "decode_levels", "make_landscape",
     "product_restriction", "quantile_restrictions", "make_session",
     "config_c1", "config_c2", "config_c3", "config_c4", "config_c5_population",
-    "tiny_session", "Simulation", "make_simulation", "LoopDraws", "loop_draws",
+    "tiny_session", "Simulation", "make_simulation", "LoopDraws", "loop_draws", "table2_problems",
 ]
 
 
@@ -341,3 +341,17 @@ def loop_draws(seed: int, samples: int, d: int, designs: int = 32, repl: int = 4
             perm[m, j] = rng.permutation(samples)
     off = rng.random((designs, d, samples))
     return LoopDraws(perm, off, rng.random(repl))
+
+
+def table2_problems(seed: int = 0) -> List[Simulation]:
+    """Three simulated problems sized like the paper's test kernels (Table II):
+    a 82,944-point 9-parameter grid restricted to about 17,956 configurations
+    with none failing; an 18,432-point 7-parameter grid restricted to about
+    9,400 of which 38.5% fail when run; an 8,184-point 6-parameter grid,
+    unrestricted, 3.9% failing.  Synthetic landscapes stand in for the
+    measured run times, which are not available."""
+    return [
+        make_simulation(seed * 3 + 1, (4, 4, 4, 4, 4, 3, 3, 3, 3), invalid_frac=1 - 17956 / 82944, hidden_frac=0.0),
+        make_simulation(seed * 3 + 2, (8, 8, 6, 4, 3, 2, 2), invalid_frac=1 - 9400 / 18432, hidden_frac=0.385),
+        make_simulation(seed * 3 + 3, (31, 11, 3, 2, 2, 2), invalid_frac=0.0, hidden_frac=0.039),
+    ]

@@ -74,6 +74,13 @@ def test_maximin_design_matches_oracle():
         assert BL.maximin_lhs(levels, dr.perm, dr.off).tolist() == OL.maximin_design(levels, dr.perm, dr.off)
 
 
+def test_mdf_matches_oracle():
+    t = np.random.default_rng(3).uniform(0.01, 1.0, size=(5, 3))
+    m, sd = BL.mean_deviation_factor(t)
+    ref = OL.mdf(t.tolist())
+    assert np.allclose(m, [a for a, _ in ref], rtol=1e-14) and np.allclose(sd, [b for _, b in ref], rtol=1e-12)
+
+
 def test_unknown_strategy():
     sim = W.make_simulation(1, (3, 3))
     with pytest.raises(ValueError):

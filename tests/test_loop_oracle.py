@@ -92,6 +92,29 @@ def test_mae_definition():
     assert OL.incumbents([5.0, float("nan"), 4.0, 6.0]) == [5.0, 5.0, 4.0, 4.0]
 
 
+def test_mdf_definition():
+    # two problems on different scales: only the ratios within a problem count
+    t = [[1.0, 100.0], [3.0, 300.0]]
+    assert OL.mdf(t) == [(0.5, 0.0), (1.5, 0.0)]
+    t = [[1.0, 2.0], [1.0, 6.0]]
+    (m0, s0), (m1, s1) = OL.mdf(t)
+    assert m0 == pytest.approx((1.0 + 0.5) / 2) and s0 == pytest.approx(0.25)
+    assert m1 == pytest.approx((1.0 + 1.5) / 2) and s1 == pytest.approx(0.25)
+    # the factors of one problem average to one
+    rng = np.random.default_rng(0)
+    t = rng.uniform(0.1, 2.0, size=(5, 3)).tolist()
+    assert sum(m for m, _ in OL.mdf(t)) / 5 == pytest.approx(1.0)
+
+
+def test_table2_problem_sizes():
+    ps = W.table2_problems(0)
+    assert [p.N for p in ps] == [82944, 18432, 8184]
+    valid = [int((p.invalid == 0).sum()) for p in ps]
+    assert abs(valid[0] - 17956) < 0.1 * 17956 and abs(valid[1] - 9400) < 0.01 * 9400 and valid[2] == 8184
+    assert ps[0].hidden.sum() == 0
+    assert abs(ps[1].hidden.sum() / valid[1] - 0.385) < 0.03 and abs(ps[2].hidden.sum() / 8184 - 0.039) < 0.01
+
+
 @pytest.mark.parametrize("strategy", ["ei", "poi", "lcb", "multi", "advanced_multi"])
 def test_run_invariants(strategy):
     sim = W.make_simulation(7, (6, 5, 4, 3), invalid_frac=0.2, hidden_frac=0.08)
