@@ -119,11 +119,13 @@ __device__ __forceinline__ double buffer_load_f64(__amdgpu_buffer_rsrc_t r, int 
 }
 
 // Last-block ticket: returns true in exactly one workgroup of the launch,
-// after every workgroup has published its partial with a device-scope fence.
+// after every workgroup has published its partial.  The partial must be
+// written by thread 0, which alone orders it before its ticket with a
+// device-scope fence (one fence per workgroup, not one per wave).
 __device__ __forceinline__ bool last_block(uint32_t* ticket, int* s_flag) {
-  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
+    __threadfence();
     const uint32_t t = atomicAdd(ticket, 1u);
     *s_flag = (t == gridDim.x - 1) ? 1 : 0;
   }

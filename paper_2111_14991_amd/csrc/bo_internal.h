@@ -16,7 +16,8 @@ constexpr int kTile = 32;           // fit tile edge (FP64)
 constexpr int kSmallFitMax = 256;   // most observations of the one-workgroup fit (batched, served, append)
 constexpr int kPlainSmallMax = 128; // a single session's fit above this uses the multi-workgroup fit
 constexpr int kAcqThreads = 256;
-constexpr int kAcqPerThread = 8;
+constexpr int kAcqPerThread = 2;
+constexpr int kAcqMaxBlocks = 512;
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 

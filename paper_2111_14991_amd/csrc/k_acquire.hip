@@ -12,7 +12,7 @@ __global__ __launch_bounds__(kAcqThreads) void k_acquire(AcqKArgs a) {
   __shared__ Best s_best[kAcqThreads / 64];
   __shared__ int s_nan[kAcqThreads / 64];
   __shared__ int s_last;
-  const int64_t per = (int64_t)kAcqThreads * kAcqPerThread;
+  const int64_t per = (a.n_valid + gridDim.x - 1) / gridDim.x;
   const int64_t c0 = (int64_t)blockIdx.x * per;
   const int64_t c1 = c0 + per < a.n_valid ? c0 + per : a.n_valid;
   acq_range<F32>(a, c0, c1, &a.slots[blockIdx.x], s_best, s_nan);
@@ -44,10 +44,12 @@ __global__ void k_scatter_post(int64_t N, const int32_t* inv_map, const uint8_t*
 
 }  // namespace
 
+// Workgroups of one acquisition launch: kAcqPerThread candidates per thread,
+// at most kAcqMaxBlocks (each publishes a slot behind a device-scope fence).
 int64_t acquire_blocks(int64_t n_valid) {
   const int64_t per = (int64_t)kAcqThreads * kAcqPerThread;
   const int64_t g = (n_valid + per - 1) / per;
-  return g > 0 ? g : 1;
+  return g < 1 ? 1 : (g > kAcqMaxBlocks ? kAcqMaxBlocks : g);
 }
 
 hipError_t launch_acquire(const DevPtrs& P, const Layout& Lo, int64_t n_valid, const uint8_t* visited,

@@ -215,7 +215,9 @@ bool make_layout(const bo_problem& p, Layout* L) {
   const size_t Np = (size_t)o.N_pad, np = (size_t)o.n_max_pad;
   const size_t post_el = p.precision == BO_FP64 ? 8 : 4;
   o.n_vslots = (int64_t)(Np / 16);
-  o.n_aslots = acquire_blocks(o.N_pad);
+  // one slot per acquisition workgroup of a plain step, or per chunk of the
+  // batched and served steps (at least 2048 candidates each)
+  o.n_aslots = std::max<int64_t>(acquire_blocks(o.N_pad), (o.N_pad + 2047) / 2048);
   o.off_st = take(sizeof(DevState));
   o.off_res = take(sizeof(bo_acq_result));
   o.off_X64 = take((size_t)o.d * Np * 8);
