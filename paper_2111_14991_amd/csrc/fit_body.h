@@ -277,7 +277,7 @@ __device__ void op_gemm(double* C, const FitArgs& a, int ti, int tj, const Tile&
 // row_newbcast, a VALU move; N is a compile-time constant).
 template <int N>
 __device__ __forceinline__ double row_bcast_d(double v) {
-  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + N, 0xf, 0xf, false);
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + N, 0xf, 0xf, true);
 }
 
 // Row Q of v (lanes 16Q .. 16Q+15) copied to all four rows: the lane swaps
@@ -395,10 +395,9 @@ __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s
       auto step = [&](auto pc) {
         constexpr int p = decltype(pc)::value;
         const double piv = readlane_d(d[p >> 2], 16 * (p & 3) + p);
-        const double dpc = row_copy_d<p & 3>(d[p >> 2]);
-        const int R = k * T + o + p;
-        bad |= !(piv > (R < a.n ? thr : 0.0)) || !(piv < INFINITY);
-        if (R < a.n) pm = fmin(pm, piv);
+        // D_pc: row p of the lane's column (an LDS-crossbar read whose
+        // latency the reciprocal's refinement covers)
+        const double dpc = __shfl(d[p >> 2], 16 * (p & 3) + c, 64);
         double rp = __builtin_amdgcn_rcp(piv);
         double e = fma(-piv, rp, 1.0);
         rp = fma(rp, e, rp);
@@ -426,6 +425,16 @@ __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s
       step(std::integral_constant<int, 13>());
       step(std::integral_constant<int, 14>());
       step(std::integral_constant<int, 15>());
+      // pivot test of the lane's column (every lane of a column holds its
+      // pivot), reduced over the wave: off the pivot-to-pivot chain
+      {
+        const int R = k * T + o + c;
+        const bool fails = !(pcol > (R < a.n ? thr : 0.0)) || !(pcol < INFINITY);
+        bad |= __ballot(fails) != 0;
+        double mn = R < a.n ? pcol : INFINITY;
+        for (int off = 1; off < 16; off <<= 1) mn = fmin(mn, __shfl_xor(mn, off, 64));
+        pm = fmin(pm, mn);
+      }
       // sqrt(pivot) and 1 / sqrt(pivot) of the lane's column: hardware
       // reciprocal square root, two Goldschmidt steps, a Newton correction
       // of each
