@@ -50,7 +50,7 @@ from typing import Callable, List, Optional, Sequence
 
 import numpy as np
 
-from . import Acq, GP, OK, normalize_grid, step
+from . import Acq, GP, E_NO_CANDIDATE, OK, OracleError, normalize_grid, step
 
 AF_NAMES = ("ei", "poi", "lcb")
 
@@ -269,6 +269,15 @@ class _Run:
         self.tr.states.append((obs, y, self.visited.copy() if vis is None else vis, acq))
         return self.do_eval(c, who)
 
+    def stepped(self, r) -> bool:
+        """True to go on; False when nothing is left to choose; raises on
+        any other failure of the step."""
+        if r.status == E_NO_CANDIDATE:
+            return False
+        if r.status != OK:
+            raise OracleError(r.status, "loop step")
+        return True
+
     def acq(self, var_s: float) -> Acq:
         if self.p.lambda_mode == 0:
             return Acq(mode=0, lambda_const=self.p.lambda_const)
@@ -297,7 +306,7 @@ class _Run:
             if strat in AF_NAMES:
                 ac = self.acq(var_s)
                 r = step(self.X, self.invalid, self.visited, obs, y, self.p.gp, ac, check=False)
-                if r.status != OK:
+                if not self.stepped(r):
                     break
                 if var_s == 0.0:
                     var_s = r.var_mean
@@ -306,7 +315,7 @@ class _Run:
             elif strat == "multi":
                 ac = self.acq(var_s)
                 r = step(self.X, self.invalid, self.visited, obs, y, self.p.gp, ac, check=False)
-                if r.status != OK:
+                if not self.stepped(r):
                     break
                 if var_s == 0.0:
                     var_s = r.var_mean
@@ -342,7 +351,7 @@ class _Run:
                         break
                     ac = self.acq(var_s)
                     r = step(self.X, self.invalid, self.visited, obs, y, self.p.gp, ac, check=False)
-                    if r.status != OK:
+                    if not self.stepped(r):
                         ended = True
                         break
                     if var_s == 0.0:

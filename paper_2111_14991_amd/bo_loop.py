@@ -196,10 +196,14 @@ class TuningRun:
         return bo.AcqParams(mode=1, mu_s=self.mu_s, var_s_mean=self.var_s)
 
     def _step(self):
+        """One GPU step; None when no configuration is left to choose (the
+        run ends), an exception for any other failure."""
         r = self.S.acquire(self.visited, self._acq(), check=False)
         self.tr.steps += 1
-        if r.status != self.bo.BO_OK:
+        if r.status == self.bo.BO_E_NO_CANDIDATE:
             return None
+        if r.status != self.bo.BO_OK:
+            raise RuntimeError(f"tuning step failed with status {r.status}")
         if self.var_s == 0.0:
             self.var_s = r.var_mean
         return r

@@ -43,7 +43,7 @@ class _OracleSession:
         return oracle.step(self.X, self.invalid, visited, self.obs, self.y, acq=a, check=False)
 
 
-BO = SimpleNamespace(AcqParams=_Acq, BO_OK=oracle.OK)
+BO = SimpleNamespace(AcqParams=_Acq, BO_OK=oracle.OK, BO_E_NO_CANDIDATE=oracle.E_NO_CANDIDATE)
 
 
 @pytest.mark.parametrize("strategy,kw", [("ei", {}), ("poi", {}), ("lcb", {}),
@@ -79,6 +79,19 @@ def test_mdf_matches_oracle():
     m, sd = BL.mean_deviation_factor(t)
     ref = OL.mdf(t.tolist())
     assert np.allclose(m, [a for a, _ in ref], rtol=1e-14) and np.allclose(sd, [b for _, b in ref], rtol=1e-12)
+
+
+def test_step_failure_raises():
+    # a failing step (here: every fit rejected) ends the run with an error, not silently
+    class _Failing(_OracleSession):
+        def acquire(self, visited, acq, check=True):
+            return SimpleNamespace(status=oracle.E_NOT_PD, idx=np.full(3, -1), var_mean=0.0)
+
+    sim = W.make_simulation(4, (5, 4, 3))
+    S = _Failing(sim.levels, sim.invalid)
+    with pytest.raises(RuntimeError):
+        BL.TuningRun(BO, S, sim.levels, sim.invalid, lambda i: float(sim.table[i]), W.loop_draws(1, 20, sim.d),
+                     BL.LoopParams(strategy="ei", budget=40)).run()
 
 
 def test_unknown_strategy():
