@@ -339,38 +339,63 @@ __device__ __forceinline__ f64x4 mm16_nr(const Tile& A, int ra, int ca, const f6
 // factor.  The pivots form one sequential chain, so the tile is factored by a
 // single wave, blocked in 16 x 16 sub-blocks (kb = 0..3):
 //  - the diagonal sub-block is held in registers (lane l: column l%16, rows
-//    l/16 + 4i) and factored column by column, the values each step needs
-//    passed between lanes (within a row of 16 lanes by DPP broadcasts,
-//    across rows by permutes); its inverse follows by forward substitution
-//    on the identity, row by row;
+//    l/16 + 4i) and reduced by elimination without square roots (column p
+//    kept as L_rp sqrt(D_pp), the square roots taken per column afterwards),
+//    the values each step needs passed between lanes (within a row of 16
+//    lanes by DPP broadcasts, across rows through the LDS crossbar or the
+//    lane swaps); its inverse follows through the unit factor
+//    L diag(L)^-1, row by row;
 //  - the panel L_ib = A_ib L_bb^-T and the trailing update
-//    A_ij -= L_ib L_jb^T are 16x16x16 FP64 matrix-core products;
+//    A_ij -= L_ib L_jb^T are 16x16x16 FP64 matrix-core products, one per
+//    wave and phase;
 //  - the off-diagonal inverse blocks X_ij = -X_ii sum_m L_im X_mj, i > j.
+// With `pre` (k > 0) the tile's last trailing update of the blocked
+// factorization, A_kk -= L_k,k-1 L_k,k-1^T, is applied in LDS first (pre
+// stages L_k,k-1), in the order of the matrix-core steps of op_gemm, so the
+// tile is the one a separate trailing-update launch would have left.
 // The pivot test: a pivot of a row below n must exceed n eps (amp + delta)
 // and be finite (padding rows: positive).  The factor (zeros above the
 // diagonal) is left in s1 and its inverse in s0.  Returns true when a pivot
 // fails, in every thread; *pmin takes the smallest pivot of the rows below n.
 template <int NT>
 __device__ bool op_diag(const FitArgs& a, int k, double delta, Tile& s0, Tile& s1, double (*colbuf)[64],
-                        double (*xbuf)[64], double* pmin) {
+                        double (*xbuf)[64], double* pmin, Tile* pre = nullptr) {
   const int tt = threadIdx.x;
   {
     constexpr int NQ = T * T / NT;
-    double v[NQ];
+    double v[NQ], lv[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int e = tt + q * NT;
       v[q] = a.A[tix(a, k, k, e >> 6, e & 63)];
+      if (pre) lv[q] = a.L[tix(a, k, k - 1, e >> 6, e & 63)];
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int e = tt + q * NT;
       s1[e >> 6][e & 63] = v[q];
+      if (pre) (*pre)[e >> 6][e & 63] = lv[q];
     }
   }
   __syncthreads();
   static_assert(NT >= 6 * 64, "one wave per trailing product");
   const int wv = uni(tt >> 6), lane = tt & 63, g = lane >> 4, c = lane & 15;
+  if (pre) {
+    // the ten lower 16 x 16 blocks, spread over the waves
+    for (int blk = wv; blk < 10; blk += NT / 64) {
+      int ib, jb;
+      tri_decode(blk, &ib, &jb);
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = mm16_nt(*pre, 16 * ib, 16 * kk, *pre, 16 * jb, 16 * kk, acc, lane);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        double& t = s1[16 * ib + g + 4 * i][16 * jb + c];
+        t = t - acc[i];
+      }
+    }
+    __syncthreads();
+  }
   const double thr = (double)a.n * 2.220446049250313e-16 * (a.amp + delta);
   bool bad = false;  // wave 0
   double pm = INFINITY;

@@ -33,32 +33,58 @@ __global__ __launch_bounds__(TT) void k_fitL_build(FitArgs a, int attempt) {
 
 constexpr int kAThreads = 2 * TT;
 
-__global__ __launch_bounds__(kAThreads) void k_fitL_A(FitArgs a, int k, int attempt) {
+// Step k of the large fit in one launch.  Workgroups b < NB each factor the
+// diagonal tile k (step k-1's update of it applied in LDS), then bring their
+// own input up to date -- the trailing tile (b, k) or the inverse tile
+// (k, b) of step k-1 -- and compute item b of step k: the panel tile L_bk
+// (b > k), the tiles L_kk, L_kk^-1 (b = k), or the inverse tile X_kb (b < k).
+// The workgroups after NB take step k-1's other trailing and inverse tiles,
+// which nothing in this launch reads.  Step k-1's items keep their
+// arithmetic and order, so the factor is the one a launch per half-step
+// would give.
+__global__ __launch_bounds__(kAThreads) void k_fitL_step(FitArgs a, int k, int attempt) {
   extern __shared__ __align__(16) unsigned char s_raw[];
   Tile* tiles = reinterpret_cast<Tile*>(s_raw);
   __shared__ __align__(16) double s_colbuf[2][64];
   __shared__ __align__(16) double s_xbuf[2][64];
   if (a.st->status != BO_OK || a.st->fail_flag) return;
+  const int NB = a.NB, tt = threadIdx.x;
+  const int m = NB - k;  // step k-1's trailing tiles span rows and columns k .. NB-1
+  if ((int)blockIdx.x >= NB) {
+    // step k-1's trailing tiles off column k, then its inverse tiles below row k
+    const int v = (int)blockIdx.x - NB, ntr = (m - 1) * m / 2;
+    int t;
+    if (v < ntr) {
+      int i, j;
+      tri_decode(v, &i, &j);
+      t = (i + 1) * (i + 2) / 2 + j + 1;
+    } else {
+      t = m * (m + 1) / 2 + k + (v - ntr);
+    }
+    stepB_item(a, k - 1, t, tiles[0], tiles[1], tt % TT, tt < TT);
+    return;
+  }
+  const int b = blockIdx.x;
   double pmin = INFINITY;
   const bool fail = op_diag<kAThreads>(a, k, jitter_of(a.noise, a.amp, attempt), tiles[0], tiles[1], s_colbuf,
-                                       s_xbuf, &pmin);
+                                       s_xbuf, &pmin, k > 0 ? &tiles[2] : nullptr);
   // launches run in order: block 0 folds this tile's pivots into the factor's minimum
-  if (!fail && blockIdx.x == 0 && threadIdx.x == 0) a.st->min_piv = fmin(k == 0 ? INFINITY : a.st->min_piv, pmin);
+  if (!fail && b == 0 && tt == 0) a.st->min_piv = fmin(k == 0 ? INFINITY : a.st->min_piv, pmin);
   if (fail) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (b == 0 && tt == 0) {
       a.st->fail_flag = 1;
       a.st->attempt = attempt;
     }
     return;
   }
-  stepA_item(a, k, blockIdx.x, tiles[0], tiles[1], tiles[2], threadIdx.x % TT, threadIdx.x < TT);
-}
-
-__global__ __launch_bounds__(TT) void k_fitL_B(FitArgs a, int k) {
-  extern __shared__ __align__(16) unsigned char s_raw[];
-  Tile* tiles = reinterpret_cast<Tile*>(s_raw);
-  if (a.st->status != BO_OK || a.st->fail_flag) return;
-  stepB_item(a, k, blockIdx.x, tiles[0], tiles[1], threadIdx.x, true);
+  if (k > 0 && b != k) {
+    // step k-1's item for tile (b, k) (trailing) or (k, b) (inverse); tiles
+    // 1 and 2 are free here, tile 0 holds L_kk^-1
+    const int t = b > k ? (b - k) * (b - k + 1) / 2 : m * (m + 1) / 2 + b;
+    stepB_item(a, k - 1, t, tiles[1], tiles[2], tt % TT, tt < TT);
+    __syncthreads();
+  }
+  stepA_item(a, k, b, tiles[0], tiles[1], tiles[2], tt % TT, tt < TT);
 }
 
 __global__ __launch_bounds__(TT) void k_fitL_alpha_z(FitArgs a) {
@@ -115,8 +141,7 @@ hipError_t prepare() {
   if (done) return hipSuccess;
   hipError_t e = set_lds((const void*)k_fit_small, kSmallLdsBytes);
   if (e == hipSuccess) e = set_lds((const void*)k_append, kSmallLdsBytes);
-  if (e == hipSuccess) e = set_lds((const void*)k_fitL_A, 3 * sizeof(Tile));
-  if (e == hipSuccess) e = set_lds((const void*)k_fitL_B, 2 * sizeof(Tile));
+  if (e == hipSuccess) e = set_lds((const void*)k_fitL_step, 3 * sizeof(Tile));
   if (e == hipSuccess) done = true;
   return e;
 }
@@ -156,12 +181,10 @@ hipError_t launch_fit_large(const DevPtrs& P, const Layout& Lo, const GpConst& g
   else hipLaunchKernelGGL(k_fitL_rearm, dim3(1), dim3(64), 0, st, P.st);
   hipLaunchKernelGGL(k_fitL_build, dim3(NB * (NB + 1) / 2), dim3(TT), 0, st, a, attempt);
   for (int k = 0; k < NB; ++k) {
-    hipLaunchKernelGGL(k_fitL_A, dim3(NB), dim3(kAThreads), 3 * sizeof(Tile), st, a, k, attempt);
-    if (k + 1 < NB) {
-      const int m = NB - 1 - k;
-      const int nb = m * (m + 1) / 2 + m * (k + 1);
-      hipLaunchKernelGGL(k_fitL_B, dim3(nb), dim3(TT), 2 * sizeof(Tile), st, a, k);
-    }
+    // NB workgroups for step k, plus step k-1's tiles that no item of step k reads
+    const int m = NB - k;
+    const int extra = k > 0 ? (m - 1) * m / 2 + k * (m - 1) : 0;
+    hipLaunchKernelGGL(k_fitL_step, dim3(NB + extra), dim3(kAThreads), 3 * sizeof(Tile), st, a, k, attempt);
   }
   const int rows = a.n_pad / (TT / 64);
   hipLaunchKernelGGL(k_fitL_alpha_z, dim3(rows), dim3(TT), 0, st, a);
