@@ -128,6 +128,27 @@ def test_fit_matches_oracle(bo):
     assert info.mean_y == pytest.approx(f.mean_y, rel=1e-15)
 
 
+@pytest.mark.parametrize("n", [200, 520, 1000])
+def test_large_fit_matches_oracle(bo, n):
+    # the multi-workgroup fit (one launch per blocked step) against the
+    # oracle's Cholesky: alpha and L^-1 normwise, scaled by the condition
+    # of K that the errors of both sides grow with
+    s = W.make_session(40 + n, (4,) * 8, n, invalid_frac=0.2)
+    S = _session(bo, s, "fp64")
+    S.fit(s.obs_idx, s.y)
+    rc, info, alpha, Linv = S.fit_read(True, True)
+    assert rc == 0 and info.status == 0
+    X = oracle.normalize_grid(s.levels)
+    f = oracle.fit(X[s.obs_idx], s.y)
+    Li = np.linalg.inv(f.L)
+    cond = np.linalg.cond(f.L @ f.L.T)
+    tol = 1e-15 * cond * n
+    assert np.max(np.abs(alpha - f.alpha)) <= tol * np.max(np.abs(f.alpha)), (np.max(np.abs(alpha - f.alpha)), tol)
+    assert np.max(np.abs(Linv - Li)) <= tol * np.max(np.abs(Li))
+    assert info.jitter == f.jitter and info.f_best == f.f_best
+    S.close()
+
+
 @pytest.mark.parametrize("n", [3, 300])
 def test_jitter_escalation_and_not_pd(bo, n):
     # duplicate observations with zero noise make K_nn singular
