@@ -289,22 +289,35 @@ __global__ __launch_bounds__(kThreads) void k_post_bf16x3(PostArgs p, int ntiles
       __syncthreads();
     }
 
-    // squared column sums; output register i of lane L holds row
-    // 8(i/4) + 4(L/32) + i%4 of the row group, column L%32
+    // squared row sums over the wave's columns; output register i of lane L
+    // holds row 8(i/4) + 4(L/32) + i%4 of the row group, column L%32.  A
+    // transposing butterfly over the 32 lanes of a half-wave: at each of the
+    // lane distances 16, 8, 4, 2 a lane keeps half of its partial sums and
+    // adds its partner's copies of them, so 16 + 8 + 4 + 2 + 1 values move
+    // instead of 16 x 5; lane L ends with register i = (L % 32) / 2.
 #pragma unroll
     for (int rg = 0; rg < 2; ++rg) {
+      float v[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        float v = 0.f;
+        float t = 0.f;
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) v = fmaf(acc[q][rg][i], acc[q][rg][i], v);
-        v += __shfl_xor(v, 1, 64);
-        v += __shfl_xor(v, 2, 64);
-        v += __shfl_xor(v, 4, 64);
-        v += __shfl_xor(v, 8, 64);
-        v += __shfl_xor(v, 16, 64);
-        if ((lane & 31) == 0) S.sq[w][32 * rg + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3)] = v;
+        for (int q = 0; q < kQ; ++q) t = fmaf(acc[q][rg][i], acc[q][rg][i], t);
+        v[i] = t;
       }
+#pragma unroll
+      for (int h = 8; h >= 1; h >>= 1) {
+        const bool up = (lane & (2 * h)) != 0;  // keeps the upper half
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+          const float send = up ? v[j] : v[h + j];
+          const float keep = up ? v[h + j] : v[j];
+          v[j] = keep + __shfl_xor(send, 2 * h, 64);
+        }
+      }
+      v[0] += __shfl_xor(v[0], 1, 64);
+      const int i = (lane & 31) >> 1;
+      if ((lane & 1) == 0) S.sq[w][32 * rg + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3)] = v[0];
     }
     // mean: the four lanes l, l+16, l+32, l+48 share a candidate
     mu_acc += shfl_xor_d(mu_acc, 16);
