@@ -662,6 +662,74 @@ __device__ void alpha_a_row(const FitArgs& a, int i, int lane) {
   if (lane == 0) a.alpha[i] = i < a.n ? v : 0.0;
 }
 
+// The same two products in one workgroup (n_pad <= 256): each wave takes
+// four of its rows (z) or columns (alpha) at a time and issues all their
+// loads before the first reduction, so a wave waits once per four rows
+// instead of once per row.  Every lane sums its terms in the order of
+// alpha_z_row / alpha_a_row and the reduction is the same, so the results
+// are the same bits.
+__device__ void alpha_z_block(const FitArgs& a, double m, int wave, int NW, int lane) {
+  for (int i0 = wave; i0 < a.n_pad; i0 += 4 * NW) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < kSmallFitMax / 64; ++c) {
+      const int j = 64 * c + lane;
+      if (64 * c < a.n_pad) {
+        const double yj = j < a.n ? a.y[j] - m : 0.0;
+        double l[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + r * NW;
+          l[r] = (i < a.n && j <= i) ? a.Linv[(size_t)i * a.ld + j] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + r * NW;
+          if (i < a.n && j <= i) v[r] += l[r] * yj;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      for (int off = 32; off > 0; off >>= 1) v[r] += shfl_xor_d(v[r], off);
+      const int i = i0 + r * NW;
+      if (lane == 0 && i < a.n_pad) a.z[i] = v[r];
+    }
+  }
+}
+
+// out(i, sum_{j >= i, j < nj} Linv[j][i] src(j)) for the columns i < ni of
+// the wave, four at a time (alpha = L^-T z; also the new row of L^-1 in an
+// append)
+template <typename Src, typename Out>
+__device__ void lt_cols_block(const FitArgs& a, int ni, int nj, Src src, Out out, int wave, int NW, int lane) {
+  for (int i0 = wave; i0 < ni; i0 += 4 * NW) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < kSmallFitMax / 64; ++c) {
+      double l[4], x[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + r * NW, j = i + 64 * c + lane;
+        const bool on = i < ni && j < nj;
+        l[r] = on ? a.Linv[(size_t)j * a.ld + i] : 0.0;
+        x[r] = on ? src(j) : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + r * NW, j = i + 64 * c + lane;
+        if (i < ni && j < nj) v[r] += l[r] * x[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      for (int off = 32; off > 0; off >>= 1) v[r] += shfl_xor_d(v[r], off);
+      const int i = i0 + r * NW;
+      if (i < ni) out(i, v[r]);
+    }
+  }
+}
+
 // ---- packing of L^-1 for the matrix-core posterior kernels ----
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
@@ -812,9 +880,14 @@ __device__ void fit_small_run(const FitArgs& a, unsigned char* s_raw) {
     return;
   }
   const double m = a.st->mean_y;
-  for (int i = wave; i < a.n_pad; i += nwave) alpha_z_row(a, i, m, lane);
+  alpha_z_block(a, m, wave, nwave, lane);
   __syncthreads();
-  for (int i = wave; i < a.n_pad; i += nwave) alpha_a_row(a, i, lane);
+  lt_cols_block(
+      a, a.n_pad, a.n, [&](int j) { return a.z[j]; },
+      [&](int i, double v) {
+        if (lane == 0) a.alpha[i] = i < a.n ? v : 0.0;
+      },
+      wave, nwave, lane);
   int64_t nfrag;
   const int64_t ne = pack_count(a, &nfrag);
   for (int64_t e = threadIdx.x; e < ne; e += kSmallThreads) {
@@ -918,17 +991,20 @@ __device__ void append_run(const FitArgs& a, unsigned char* s_raw) {
   const double dg = sqrt(piv);
   const double inv_dg = 1.0 / dg;
   // new rows: L[n0] = (l, d), L^-1[n0] = (-(l^T L^-1) / d, 1 / d), K0 row and column
-  for (int i = t; i <= n0; i += nt) {
-    double w = 0.0;
-    for (int j = i; j < n0; ++j) w += s_l[j] * a.Linv[(size_t)j * a.ld + i];
-    a.L[(size_t)n0 * a.ld + i] = i < n0 ? s_l[i] : dg;
-    a.Linv[(size_t)n0 * a.ld + i] = i < n0 ? -w * inv_dg : inv_dg;
-    if (a.K0) {
-      const double kv = i < n0 ? s_k[i] : a.amp;
-      a.K0[(size_t)n0 * a.ld + i] = kv;
-      a.K0[(size_t)i * a.ld + n0] = kv;
-    }
-  }
+  lt_cols_block(
+      a, n0 + 1, n0, [&](int j) { return s_l[j]; },
+      [&](int i, double w) {
+        if (lane == 0) {
+          a.L[(size_t)n0 * a.ld + i] = i < n0 ? s_l[i] : dg;
+          a.Linv[(size_t)n0 * a.ld + i] = i < n0 ? -w * inv_dg : inv_dg;
+          if (a.K0) {
+            const double kv = i < n0 ? s_k[i] : a.amp;
+            a.K0[(size_t)n0 * a.ld + i] = kv;
+            a.K0[(size_t)i * a.ld + n0] = kv;
+          }
+        }
+      },
+      wave, nwave, lane);
   // mean and incumbent over all observations, in the reduction order of fit_gather
   s_red[t] = t < a.n ? a.y[t] : 0.0;
   s_red[nt + t] = t < a.n ? a.y[t] : INFINITY;
@@ -949,9 +1025,14 @@ __device__ void append_run(const FitArgs& a, unsigned char* s_raw) {
   }
   __threadfence_block();
   __syncthreads();
-  for (int i = wave; i < a.n_pad; i += nwave) alpha_z_row(a, i, m, lane);
+  alpha_z_block(a, m, wave, nwave, lane);
   __syncthreads();
-  for (int i = wave; i < a.n_pad; i += nwave) alpha_a_row(a, i, lane);
+  lt_cols_block(
+      a, a.n_pad, a.n, [&](int j) { return a.z[j]; },
+      [&](int i, double v) {
+        if (lane == 0) a.alpha[i] = i < a.n ? v : 0.0;
+      },
+      wave, nwave, lane);
   // packed operand: the column blocks from the one holding row n0 on (the
   // fragment order does not depend on n for the 16x16x4 layout)
   const int J0 = n0 / 16, JB = a.n_pad / 16;
