@@ -668,24 +668,29 @@ __device__ void alpha_a_row(const FitArgs& a, int i, int lane) {
 // instead of once per row.  Every lane sums its terms in the order of
 // alpha_z_row / alpha_a_row and the reduction is the same, so the results
 // are the same bits.
-__device__ void alpha_z_block(const FitArgs& a, double m, int wave, int NW, int lane) {
-  for (int i0 = wave; i0 < a.n_pad; i0 += 4 * NW) {
+// out(i, sum_{j <= i} Linv[i][j] src(j)) for the rows i < ni of the wave
+// (zero for rows at or beyond nv), four at a time (z = L^-1 (y - m); also
+// L^-1 k in an append)
+template <typename Src, typename Out>
+__device__ void l_rows_block(const FitArgs& a, int ni, int nv, Src src, Out out, int wave, int NW, int lane) {
+  for (int i0 = wave; i0 < ni; i0 += 4 * NW) {
     double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < kSmallFitMax / 64; ++c) {
       const int j = 64 * c + lane;
-      if (64 * c < a.n_pad) {
-        const double yj = j < a.n ? a.y[j] - m : 0.0;
-        double l[4];
+      if (64 * c < ni) {
+        double l[4], x[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = i0 + r * NW;
-          l[r] = (i < a.n && j <= i) ? a.Linv[(size_t)i * a.ld + j] : 0.0;
+          const bool on = i < nv && j <= i;
+          l[r] = on ? a.Linv[(size_t)i * a.ld + j] : 0.0;
+          x[r] = on ? src(j) : 0.0;
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = i0 + r * NW;
-          if (i < a.n && j <= i) v[r] += l[r] * yj;
+          if (i < nv && j <= i) v[r] += l[r] * x[r];
         }
       }
     }
@@ -693,7 +698,7 @@ __device__ void alpha_z_block(const FitArgs& a, double m, int wave, int NW, int 
     for (int r = 0; r < 4; ++r) {
       for (int off = 32; off > 0; off >>= 1) v[r] += shfl_xor_d(v[r], off);
       const int i = i0 + r * NW;
-      if (lane == 0 && i < a.n_pad) a.z[i] = v[r];
+      if (i < ni) out(i, v[r]);
     }
   }
 }
@@ -880,7 +885,12 @@ __device__ void fit_small_run(const FitArgs& a, unsigned char* s_raw) {
     return;
   }
   const double m = a.st->mean_y;
-  alpha_z_block(a, m, wave, nwave, lane);
+  l_rows_block(
+      a, a.n_pad, a.n, [&](int j) { return a.y[j] - m; },
+      [&](int i, double v) {
+        if (lane == 0) a.z[i] = v;
+      },
+      wave, nwave, lane);
   __syncthreads();
   lt_cols_block(
       a, a.n_pad, a.n, [&](int j) { return a.z[j]; },
@@ -965,13 +975,13 @@ __device__ void append_run(const FitArgs& a, unsigned char* s_raw) {
     s_k[i] = a.amp * matern64(a.nu2, sqrt(s2), a.inv_l);
   }
   __syncthreads();
-  // l = L^-1 k, one row per wave
-  for (int j = wave; j < n0; j += nwave) {
-    double v = 0.0;
-    for (int i = lane; i <= j; i += 64) v += a.Linv[(size_t)j * a.ld + i] * s_k[i];
-    for (int off = 32; off > 0; off >>= 1) v += shfl_xor_d(v, off);
-    if (lane == 0) s_l[j] = v;
-  }
+  // l = L^-1 k
+  l_rows_block(
+      a, n0, n0, [&](int j) { return s_k[j]; },
+      [&](int i, double v) {
+        if (lane == 0) s_l[i] = v;
+      },
+      wave, nwave, lane);
   __syncthreads();
   // new pivot d^2 = amp + delta - |l|^2 (fixed-order tree)
   s_red[t] = t < n0 ? s_l[t] * s_l[t] : 0.0;
@@ -1025,7 +1035,12 @@ __device__ void append_run(const FitArgs& a, unsigned char* s_raw) {
   }
   __threadfence_block();
   __syncthreads();
-  alpha_z_block(a, m, wave, nwave, lane);
+  l_rows_block(
+      a, a.n_pad, a.n, [&](int j) { return a.y[j] - m; },
+      [&](int i, double v) {
+        if (lane == 0) a.z[i] = v;
+      },
+      wave, nwave, lane);
   __syncthreads();
   lt_cols_block(
       a, a.n_pad, a.n, [&](int j) { return a.z[j]; },
