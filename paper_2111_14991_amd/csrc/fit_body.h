@@ -137,24 +137,18 @@ __device__ void fit_gather(const FitArgs& a, double* s_red, int* s_pos, int* s_b
     }
   }
   __syncthreads();
-  // coordinates: one (observation, dimension) pair per thread and round, in
-  // groups of 8 rounds
-  const int ne = a.n_pad * kMaxD;
-  for (int e0 = t; e0 < ne; e0 += 8 * nt) {
-    double x[8];
+  // coordinates: one observation per thread, its kMaxD loads issued
+  // together (one round for n_pad <= blockDim.x)
+  for (int i = t; i < a.n_pad; i += nt) {
+    const bool live = i < a.n;
+    const int pos = live ? s_pos[i] : 0;
+    double x[kMaxD];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * nt;
-      const int i = e / kMaxD, j = e % kMaxD;
-      x[u] = (e < ne && i < a.n && j < a.d) ? a.X64[(int64_t)j * a.N_pad + s_pos[i]] : 0.0;
-    }
+    for (int j = 0; j < kMaxD; ++j) x[j] = (live && j < a.d) ? a.X64[(int64_t)j * a.N_pad + pos] : 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + u * nt;
-      if (e < ne) {
-        a.Xo64[e] = x[u];
-        a.Xo32[e] = (float)x[u];
-      }
+    for (int j = 0; j < kMaxD; ++j) {
+      a.Xo64[(size_t)i * kMaxD + j] = x[j];
+      a.Xo32[(size_t)i * kMaxD + j] = (float)x[j];
     }
   }
   // fixed-order tree reductions of the sum and the minimum
