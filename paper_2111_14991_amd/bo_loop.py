@@ -99,10 +99,17 @@ def maximin_lhs(levels: Sequence[int], perm: np.ndarray, off: np.ndarray) -> np.
     S = perm.shape[2]
     u = (perm + off) / S                                           # (designs, d, S)
     lv = np.minimum(np.floor(u * k[None, :, None]).astype(np.int64), (k - 1)[None, :, None])
-    den = np.maximum(k - 1, 1) ** 2
-    wt = np.lcm.reduce(den) // den                                 # (d,)
+    den = [max(int(v) - 1, 1) ** 2 for v in k]
+    L = 1
+    for v in den:
+        L = math.lcm(L, v)
     diff = lv[:, :, :, None] - lv[:, :, None, :]                   # (designs, d, S, S)
-    d2 = np.einsum("mjab,j->mab", diff * diff, wt)
+    if L * max(den) * len(den) < 2 ** 62:
+        wt = np.array([L // v for v in den], dtype=np.int64)
+        d2 = np.einsum("mjab,j->mab", diff * diff, wt)
+    else:  # beyond int64: exact Python integers
+        wt = np.array([L // v for v in den], dtype=object)
+        d2 = np.einsum("mjab,j->mab", (diff * diff).astype(object), wt)
     iu = np.triu_indices(S, 1)
     crit = d2[:, iu[0], iu[1]].min(axis=1)
     best = int(np.argmax(crit))

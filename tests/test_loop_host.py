@@ -69,7 +69,9 @@ def test_loop_matches_oracle_loop(strategy, kw):
 
 
 def test_maximin_design_matches_oracle():
-    for seed, levels in enumerate([(6, 6, 6, 6), (12, 7, 5, 3, 3, 3, 3, 3), (2, 9), (4, 3, 5)]):
+    # the last space's squared-distance scale exceeds 64-bit integers
+    for seed, levels in enumerate([(6, 6, 6, 6), (12, 7, 5, 3, 3, 3, 3, 3), (2, 9), (4, 3, 5),
+                                   (24, 30, 32, 38, 42, 44, 48)]):
         dr = W.loop_draws(seed, 20, len(levels))
         assert BL.maximin_lhs(levels, dr.perm, dr.off).tolist() == OL.maximin_design(levels, dr.perm, dr.off)
 
