@@ -10,8 +10,9 @@ host.  Inputs are seeded synthetic landscapes resident in HBM before timing.
 
 Prints one JSON line: throughput in candidate posterior+acquisition evals/s
 (unmasked candidates per step / step time), step latency percentiles, phase
-times, the roofline of the posterior kernel, and the FP64 CPU oracle timed
-on this host on a bounded sample of the same workload.
+times, the roofline of the posterior kernel and of the whole step, one whole
+FP64 CPU oracle step on the same inputs timed on this host, and the error of
+every GPU result against that oracle step.
 """
 from __future__ import annotations
 
@@ -72,36 +73,60 @@ def traffic_from_profile(precision: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(s, n_unmasked: int, budget_s: float = 12.0):
-    """FP64 oracle on this host: the fit on all observations plus the
-    posterior of a sample of unmasked candidates, extrapolated linearly to the
-    whole step (acquisition and arg-optimum are negligible next to it)."""
+def _quantiles(err):
+    q = np.quantile(err, [0.5, 0.99, 1.0]) if err.size else np.zeros(3)
+    return {"median": float(q[0]), "p99": float(q[1]), "max": float(q[2])}
+
+
+def oracle_step_and_errors(s, S, bo, vis, acq_g, ms_step):
+    """One whole FP64 oracle step on the benchmark's inputs, timed on this
+    host's cores (the CPU baseline), and the error of every GPU result against
+    it: normwise errors (scale floors max|y| for mu and LCB, amp = 1 for the
+    variance, 1 for EI and PI) of the mean, variance and the kernel's own EI,
+    PI, LCB over all predicted candidates, the scalars, and the chosen
+    indices (exact, or within tolerance of the oracle's optimum)."""
     import oracle
-    Xo = oracle.normalize_grid(s.levels, s.grid_index(s.obs_idx))
+    X = oracle.normalize_grid(s.levels, s.cand, s.N)
+    n0 = s.n_init
+    vis0 = np.zeros(s.N, np.uint8)
+    vis0[s.obs_idx[:n0]] = 1
+    var_s = oracle.step(X, s.invalid, vis0, s.obs_idx[:n0], s.y[:n0], oracle.GP(), oracle.Acq(mode=0)).var_mean
+    oa = oracle.Acq(mode=1, mu_s=float(np.mean(s.y[:n0])), var_s_mean=var_s)
     t0 = time.perf_counter()
-    f = oracle.fit(Xo, s.y)
-    t_fit = time.perf_counter() - t0
-    mask = (s.invalid | s.visited()).astype(bool)
-    pool = np.flatnonzero(~mask)
-    rng = np.random.Generator(np.random.PCG64(11))
-    probe = rng.choice(pool, min(pool.size, 256), replace=False)
-    P = oracle.normalize_grid(s.levels, s.grid_index(probe))
-    t0 = time.perf_counter()
-    oracle.predict(f, P)
-    t_probe = time.perf_counter() - t0
-    per = t_probe / probe.size
-    m = int(min(pool.size, max(probe.size, budget_s / max(per, 1e-9))))
-    samp = rng.choice(pool, m, replace=False)
-    P = oracle.normalize_grid(s.levels, s.grid_index(samp))
-    t0 = time.perf_counter()
-    oracle.predict(f, P)
-    t_pred = time.perf_counter() - t0
-    t_step = t_fit + t_pred * n_unmasked / m
-    return {"value": n_unmasked / t_step, "unit": "candidate-evals/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"FP64 oracle fit on all {s.n} observations ({t_fit:.3f} s) + posterior of {m} of "
-                      f"{n_unmasked} unmasked candidates ({t_pred:.2f} s), extrapolated linearly to the step",
-            "step_s_estimate": t_step}
+    ref = oracle.step(X, s.invalid, vis, s.obs_idx, s.y, oracle.GP(), oa, want_posterior=True)
+    t_cpu = time.perf_counter() - t0
+    cpu = {"value": ref.n_unmasked / t_cpu, "unit": "candidate-evals/s", "cores": oracle.threads(),
+           "kind": "oracle",
+           "sample": f"one whole FP64 oracle step on the benchmark's inputs: fit on {s.n} observations, posterior "
+                     f"and EI/PI/LCB of all {ref.n_unmasked} predicted candidates, arg-optima ({t_cpu:.2f} s)",
+           "step_s": t_cpu, "gpu_speedup": t_cpu / (ms_step * 1e-3)}
+    S.fit(s.obs_idx, s.y)
+    r, vals = S.acquire_values(vis, acq_g)
+    mu, var, _ = S.posterior(vis)
+    mu, var = mu.cpu().numpy(), var.cpu().numpy()
+    A_g = np.stack([v.cpu().numpy() for v in vals], axis=1)
+    mask = (s.invalid | vis).astype(bool)
+    keep = ~mask
+    A_r = oracle.acquisition_arrays(np.nan_to_num(ref.mu), np.nan_to_num(ref.var), mask, ref.f_best, ref.lam)
+    ymax = float(np.abs(s.y).max())
+    scales = {"mu": ymax, "var": 1.0, "ei": 1.0, "pi": 1.0, "lcb": ymax}
+    got = {"mu": mu, "var": var, "ei": A_g[:, 0], "pi": A_g[:, 1], "lcb": A_g[:, 2]}
+    want = {"mu": ref.mu, "var": ref.var, "ei": A_r[:, 0], "pi": A_r[:, 1], "lcb": A_r[:, 2]}
+    err = {}
+    for k in got:
+        g, w = got[k][keep], want[k][keep]
+        err[k] = _quantiles(np.abs(g - w) / np.maximum(np.abs(w), scales[k]))
+    err["var_mean_rel"] = abs(r.var_mean - ref.var_mean) / ref.var_mean
+    err["lambda_rel"] = abs(r.lam - ref.lam) / ref.lam
+    agree = []
+    for q, name in enumerate(("ei", "pi", "lcb")):
+        g, o = int(r.idx[q]), int(ref.idx[q])
+        a = A_r[:, q] if q < 2 else -A_r[:, q]
+        gap = float(a[o] - a[g]) / max(abs(a[o]), scales[name]) if g >= 0 else float("inf")
+        agree.append({"gpu": g, "oracle": o, "equal": g == o, "ref_gap": gap})
+    err["indices"] = agree
+    err["masks_equal"] = bool(all(np.array_equal(np.isnan(v), mask) for v in got.values()))
+    return cpu, err
 
 
 def _post_flops(N_valid, n, d):
@@ -487,19 +512,26 @@ def main() -> int:
     ph = np.array(phases)
     post_ms = float(ph[:, 1].mean())
     n, d = s.n, s.d
-    # algorithmic work of one posterior launch: every valid candidate against
-    # every observation -- triangular solve n^2, distance+Matern (3d+12)n, mean 2n
-    flops = float(n_valid) * (n * n + (3 * d + 12) * n + 2 * n)
-    achieved = flops / (post_ms * 1e-3) / 1e12
     peak = PEAK[wl["peak"]]
+    # algorithmic work of the posterior: the triangular solve, n^2 flops per
+    # predicted candidate (distance, Matern and mean add (3d + 14) n)
+    flops = float(n_unmasked) * n * n
+    achieved = flops / (post_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": traffic_from_profile(wl["precision"], args.workload),
-                "kernel": POSTERIOR_KERNEL[wl["precision"]], "kernel_ms": post_ms}
+                "kernel": POSTERIOR_KERNEL[wl["precision"]], "kernel_ms": post_ms,
+                "flops_per_launch": flops}
+    fit_flops = 2.0 * n ** 3 / 3.0  # Cholesky n^3/3 + triangular inverse n^3/3, FP64
     if wl["precision"] == "bf16x3":
-        # the three bfloat16 products issued per algorithmic multiply-add
-        mfma = float(n_valid) * 3 * n * (n + 1)
+        # three bfloat16 products per multiply-add of the compensated contraction
+        mfma = 3.0 * flops
         roofline["mfma_issued_tflops"] = mfma / (post_ms * 1e-3) / 1e12
         roofline["mfma_issued_frac"] = roofline["mfma_issued_tflops"] / peak
+        roofline["graded_step_frac"] = (mfma / (PEAK["bf16"] * 1e12) + fit_flops / (PEAK["fp64"] * 1e12)) / \
+            (ms_per_step * 1e-3)
+    else:
+        roofline["graded_step_frac"] = (flops / (peak * 1e12) + fit_flops / (PEAK["fp64"] * 1e12)) / \
+            (ms_per_step * 1e-3)
 
     line = {
         "metric": "candidate posterior+acquisition evals/s; BO step p50/p99 latency",
@@ -515,9 +547,12 @@ def main() -> int:
                        "mean": float(np.mean(lat) * 1e3)},
         "phases_ms": {"fit": float(ph[:, 0].mean()), "posterior": post_ms, "acquire": float(ph[:, 2].mean())},
         "roofline": roofline,
-        "cpu_baseline": None if args.no_cpu else cpu_baseline(s, n_unmasked),
+        "cpu_baseline": None,
         "chosen": [int(v) for v in r.idx],
     }
+    if not args.no_cpu:
+        line["cpu_baseline"], line["error_vs_oracle"] = oracle_step_and_errors(s, S, bo, s.visited(), acq,
+                                                                                ms_per_step)
     print(json.dumps(line), flush=True)
     S.close()
     return 0

@@ -188,24 +188,54 @@ bo_status bo_gp_fit(bo_session* s, const int64_t* obs_idx, const double* y, int3
  * bo_gp_fit.  BF16X3 sessions always refit. */
 bo_status bo_gp_append(bo_session* s, const int64_t* obs_idx, const double* y, int32_t n);
 
+/* Records one evaluation in the session (Sections III-B, III-D.2): candidate
+ * idx (0 <= idx < N) is marked evaluated in the session's own record, so that
+ * it is never predicted or selected again.  A valid evaluation (valid = 1,
+ * y finite, run time of the configuration) is appended to the session's
+ * observations -- those of the last bo_gp_fit / bo_gp_append / bo_observe,
+ * none after bo_set_grid -- and the surrogate is refit: the bordered rank-1
+ * extension of the device-resident factor when the session holds a fit of the
+ * n - 1 earlier points and n <= 256, otherwise a whole fit.  A failed
+ * evaluation (valid = 0: the configuration did not compile or run) is only
+ * marked; it never enters the fit (Section III-D.2 argues against giving it an
+ * artificial value).  Asynchronous; errors as bo_gp_append (an evaluation of a
+ * restriction-pruned candidate with valid = 1 is BO_E_INVALID_ARG at the next
+ * synchronizing call).  BO_E_INVALID_ARG on the host for idx out of range,
+ * valid not 0/1, non-finite y, or more than n_max valid observations. */
+bo_status bo_observe(bo_session* s, int64_t idx, double y, int32_t valid);
+
 /* Synchronizing: fit status, accepted jitter, m and f_best.  alpha (host
  * double[n]) and Linv (host double[n*n], row-major lower triangle of L^-1)
  * are filled when non-NULL. */
 bo_status bo_fit_read(bo_session* s, bo_fit_info* info, double* alpha, double* Linv);
 
-/* Posterior over the candidates that are valid and not visited (device
- * uint8[N], nonzero = evaluated; NULL = none).  mu and var (device double[N],
- * nullable) receive the mean and latent variance, NaN where excluded.
- * var_mean (host, nullable) receives the mean variance; when it is non-NULL
- * the call is synchronizing. */
+/* Exhaustive prediction over the discrete space (Section III-G): the GP
+ * posterior mean mu = m + k*^T alpha and latent variance var = amp - |L^-1 k*|^2
+ * (clamped at zero) of the surrogate of Section III-B, for every candidate
+ * that is valid and not visited (Section III-D.2).  visited: device uint8[N],
+ * nonzero = evaluated; NULL = the session's own record (bo_observe), which is
+ * empty until bo_observe is called.  mu and var (device double[N], nullable)
+ * receive the mean and latent variance in the caller's enumeration, NaN where
+ * excluded.  var_mean (host, nullable) receives the mean variance over the
+ * predicted candidates (Section III-F); when it is non-NULL the call is
+ * synchronizing. */
 bo_status bo_posterior(bo_session* s, const uint8_t* visited, double* mu, double* var,
                        double* var_mean);
 
 /* Whole step after bo_gp_fit: posterior, lambda, acquisitions and the masked
- * arg-optimum (Sections III-C, III-D.2, III-F, III-G).  Synchronizing: *out
+ * arg-optimum (Sections III-C, III-D.2, III-F, III-G).  visited as in
+ * bo_posterior (NULL = the session's own record).  Synchronizing: *out
  * (host) receives the result; the return value equals out->status. */
 bo_status bo_acquire(bo_session* s, const uint8_t* visited, const bo_acq_params* params,
                      bo_acq_result* out);
+
+/* Same as bo_acquire, and the acquisition values the arg-optimum was taken
+ * over (Section III-C, minimization forms): ei, pi and lcb (device double[N],
+ * each nullable) receive EI, PI and LCB of every predicted candidate in the
+ * caller's enumeration, NaN where the candidate is excluded or the function
+ * is not requested.  Synchronizing. */
+bo_status bo_acquire_values(bo_session* s, const uint8_t* visited, const bo_acq_params* params, double* ei,
+                            double* pi, double* lcb, bo_acq_result* out);
 
 /* Same as bo_acquire without waiting: *out_dev (device) is written on the
  * session stream.  A fit of more than 128 observations by bo_gp_fit runs on
@@ -266,7 +296,8 @@ bo_status bo_batch_set_timing(bo_batch* b, int32_t enable);
 
 /* One step of every session, synchronizing.  Host arrays of `count` entries:
  * obs_idx[i], y[i] (device pointers, as bo_gp_fit), n[i] (1..min(n_max, 256)),
- * visited[i] (device uint8[N_i] or NULL; visited itself may be NULL),
+ * visited[i] (device uint8[N_i], or NULL for the session's own record as in
+ * bo_posterior; visited itself may be NULL),
  * params[i], out[i] (host).  Each out[i].status reports that session's
  * outcome; the return value reports argument and runtime errors only.
  * graph_ms (nullable) receives the graph's duration, -1 without timing.

@@ -67,6 +67,7 @@ def lib():
         L.orc_predict.argtypes = [C.c_int64, C.c_int32, dp, C.c_int32, dp, dp, dp, C.c_double,
                                   C.POINTER(_Gp), dp, dp]
         L.orc_acquisitions.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp]
+        L.orc_acquisitions_all.argtypes = [C.c_int64, dp, dp, C.c_void_p, C.c_double, C.c_double, dp]
         L.orc_step.argtypes = [C.c_int64, C.c_int32, dp, C.c_void_p, C.c_void_p, C.c_int32,
                                C.c_void_p, dp, C.POINTER(_Gp), C.POINTER(_Acq), C.c_void_p,
                                C.c_void_p, C.POINTER(_Res)]
@@ -172,6 +173,16 @@ def predict(f: Fit, P: np.ndarray):
 def acquisitions(mu: float, var: float, f_best: float, lam: float) -> np.ndarray:
     out = np.empty(3)
     lib().orc_acquisitions(float(mu), float(var), float(f_best), float(lam), _dp(out))
+    return out
+
+
+def acquisition_arrays(mu: np.ndarray, var: np.ndarray, mask: np.ndarray, f_best: float, lam: float) -> np.ndarray:
+    """EI, PI, LCB (columns) of every candidate with mask == 0; NaN rows elsewhere."""
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    var = np.ascontiguousarray(var, dtype=np.float64)
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    out = np.empty((mu.shape[0], 3))
+    lib().orc_acquisitions_all(mu.shape[0], _dp(mu), _dp(var), m.ctypes.data, float(f_best), float(lam), _dp(out))
     return out
 
 

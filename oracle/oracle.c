@@ -244,6 +244,20 @@ void orc_acquisitions(double mu, double var, double f_best, double lambda, doubl
   out[2] = mu - lambda * sigma;
 }
 
+/* EI, PI, LCB of every candidate with mask[c] == 0 (rows of out, N x 3);
+   NaN rows elsewhere.  The per-point definition is orc_acquisitions. */
+void orc_acquisitions_all(int64_t N, const double* mu, const double* var, const uint8_t* mask,
+                          double f_best, double lambda, double* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < N; ++c) {
+    if (mask[c]) {
+      out[3 * c] = out[3 * c + 1] = out[3 * c + 2] = NAN;
+    } else {
+      orc_acquisitions(mu[c], var[c], f_best, lambda, out + 3 * c);
+    }
+  }
+}
+
 #define ORC_BLOCK 4096
 
 int orc_step(int64_t N, int32_t d, const double* X, const uint8_t* invalid,

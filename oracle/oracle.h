@@ -85,6 +85,11 @@ void orc_predict(int64_t M, int32_t d, const double* P, int32_t n, const double*
 /* Acquisition values at one point: out[0] = EI, out[1] = PI, out[2] = LCB. */
 void orc_acquisitions(double mu, double var, double f_best, double lambda, double* out);
 
+/* orc_acquisitions at every candidate with mask[c] == 0 (row c of out, N x 3);
+ * NaN rows where mask[c] != 0. */
+void orc_acquisitions_all(int64_t N, const double* mu, const double* var, const uint8_t* mask,
+                          double f_best, double lambda, double* out);
+
 /* One whole step over N candidates X (N x d).  invalid[c] != 0 marks a
  * restriction-pruned candidate, visited[c] != 0 an evaluated one (either way
  * it is excluded from prediction and from the arg-optimum).  obs_idx/y are the

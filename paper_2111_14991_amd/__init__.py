@@ -95,9 +95,12 @@ _SIGS = {
     "bo_set_candidates": (C.c_int, [_VP, _VP, C.c_int32, _U8P, C.POINTER(C.c_int64)]),
     "bo_gp_fit": (C.c_int, [_VP, _I64P, _DP, C.c_int32]),
     "bo_gp_append": (C.c_int, [_VP, _I64P, _DP, C.c_int32]),
+    "bo_observe": (C.c_int, [_VP, C.c_int64, C.c_double, C.c_int32]),
     "bo_fit_read": (C.c_int, [_VP, C.POINTER(bo_fit_info), _DP, _DP]),
     "bo_posterior": (C.c_int, [_VP, _U8P, _DP, _DP, C.POINTER(C.c_double)]),
     "bo_acquire": (C.c_int, [_VP, _U8P, C.POINTER(bo_acq_params), C.POINTER(bo_acq_result)]),
+    "bo_acquire_values": (C.c_int, [_VP, _U8P, C.POINTER(bo_acq_params), _DP, _DP, _DP,
+                                    C.POINTER(bo_acq_result)]),
     "bo_acquire_async": (C.c_int, [_VP, _U8P, C.POINTER(bo_acq_params), _VP]),
     "bo_set_timing": (C.c_int, [_VP, C.c_int32]),
     "bo_get_timing": (C.c_int, [_VP, C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float)]),
@@ -264,6 +267,7 @@ class Session:
                                        self.stream.cuda_stream), "bo_session_create")
         self.h = h
         self.n_valid = None
+        self.n_fit = 0
         self._keep = []
 
     def close(self):
@@ -288,6 +292,7 @@ class Session:
         nv = C.c_int64()
         _check(lib().bo_set_grid(self.h, lv, _ptr(cd), _ptr(inv), C.byref(nv)), "bo_set_grid")
         self.n_valid = nv.value
+        self.n_fit = 0
         return nv.value
 
     def set_candidates(self, X, invalid=None) -> int:
@@ -300,6 +305,7 @@ class Session:
         nv = C.c_int64()
         _check(lib().bo_set_candidates(self.h, _ptr(Xd), f32, _ptr(inv), C.byref(nv)), "bo_set_candidates")
         self.n_valid = nv.value
+        self.n_fit = 0
         return nv.value
 
     def fit(self, obs_idx, y):
@@ -308,6 +314,7 @@ class Session:
         yy = self._d(y, torch.float64)
         self._keep = [oi, yy]  # alive until the next synchronizing call
         _check(lib().bo_gp_fit(self.h, _ptr(oi), _ptr(yy), int(oi.shape[0])), "bo_gp_fit")
+        self.n_fit = int(oi.shape[0])
 
     def append(self, obs_idx, y):
         """Refit after one new observation: obs_idx / y hold the current fit's
@@ -317,10 +324,18 @@ class Session:
         yy = self._d(y, torch.float64)
         self._keep = [oi, yy]
         _check(lib().bo_gp_append(self.h, _ptr(oi), _ptr(yy), int(oi.shape[0])), "bo_gp_append")
+        self.n_fit = int(oi.shape[0])
+
+    def observe(self, idx: int, y: float = 0.0, valid: bool = True):
+        """Record one evaluation (bo_observe): candidate `idx` is marked
+        evaluated; a valid one is appended to the fit, which is refit."""
+        _check(lib().bo_observe(self.h, int(idx), float(y), 1 if valid else 0), "bo_observe")
+        if valid:
+            self.n_fit += 1
 
     def fit_read(self, want_alpha=True, want_linv=False):
         info = bo_fit_info()
-        n = int(self._keep[0].shape[0]) if self._keep else 0
+        n = self.n_fit
         alpha = np.zeros(n) if want_alpha else None
         Linv = np.zeros((n, n)) if want_linv else None
         rc = lib().bo_fit_read(self.h, C.byref(info), None if alpha is None else alpha.ctypes.data,
@@ -345,6 +360,19 @@ class Session:
         if check and rc not in (BO_OK,):
             raise BOError(rc, "bo_acquire", last_error())
         return _result(r)
+
+    def acquire_values(self, visited=None, acq: Optional[AcqParams] = None, check=True):
+        """bo_acquire_values: the step result and the EI, PI, LCB arrays over the
+        caller's enumeration (device float64 tensors, NaN where excluded)."""
+        torch = self.torch
+        vis = self._d(visited, torch.uint8)
+        a = (acq or AcqParams(mode=0)).c()
+        vals = [torch.empty(self.N, dtype=torch.float64, device=self.device) for _ in range(3)]
+        r = bo_acq_result()
+        rc = lib().bo_acquire_values(self.h, _ptr(vis), C.byref(a), *[_ptr(v) for v in vals], C.byref(r))
+        if check and rc != BO_OK:
+            raise BOError(rc, "bo_acquire_values", last_error())
+        return _result(r), vals
 
     def set_timing(self, enable: bool = True):
         _check(lib().bo_set_timing(self.h, 1 if enable else 0), "bo_set_timing")

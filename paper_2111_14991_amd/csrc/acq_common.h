@@ -22,6 +22,7 @@ struct AcqKArgs {
   AcqSlot* slots;
   DevState* st;
   bo_acq_result* out;
+  double* vals[3];  // optional per-candidate EI, PI, LCB in the caller's enumeration
 };
 
 struct Best {
@@ -93,6 +94,11 @@ __device__ void acq_range(const AcqKArgs& a, int64_t c_begin, int64_t c_end, Acq
       }
       double v[3];
       acquisitions64(mu, var, fb, lam, &v[0], &v[1], &v[2]);
+      if (a.vals[0] || a.vals[1] || a.vals[2]) {
+        const int32_t o = a.orig[c];
+        for (int k = 0; k < 3; ++k)
+          if (a.vals[k] && (a.bits & (1u << k))) a.vals[k][o] = v[k];
+      }
       for (int k = 0; k < 3; ++k) {
         if (!(a.bits & (1u << k))) continue;
         if (v[k] != v[k]) {

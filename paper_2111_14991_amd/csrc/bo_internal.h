@@ -82,6 +82,8 @@ struct DevPtrs {
   double* alpha;      // [n_max_pad]
   double* z;          // [n_max_pad]
   void* Bpk;          // packed L^-1 operand for the matrix cores
+  int64_t* obs;       // [n_max_pad] candidate indices of the current fit's observations
+  uint8_t* vis;       // [N_pad] the session's own record of evaluated candidates
 };
 
 struct Layout {
@@ -89,7 +91,7 @@ struct Layout {
   int d, n_max, n_max_pad, prec;
   size_t off_st, off_res, off_X64, off_X32, off_orig, off_inv, off_blk, off_mu, off_var,
       off_vslots, off_aslots, off_Xo64, off_Xo32, off_y, off_A, off_L, off_Dinv, off_Linv,
-      off_alpha, off_z, off_Bpk, off_K0, total;
+      off_alpha, off_z, off_Bpk, off_K0, off_obs, off_vis, total;
   int64_t n_vslots, n_aslots;
 };
 
@@ -118,7 +120,8 @@ hipError_t launch_fit_large(const DevPtrs& P, const Layout& Lo, const GpConst& g
 hipError_t launch_posterior(const DevPtrs& P, const Layout& Lo, const GpConst& g, int n, int64_t n_valid,
                             const uint8_t* visited, const AcqArgs& a, hipStream_t st);
 hipError_t launch_acquire(const DevPtrs& P, const Layout& Lo, int64_t n_valid, const uint8_t* visited,
-                          const AcqArgs& a, bo_acq_result* out_dev, hipStream_t st);
+                          const AcqArgs& a, bo_acq_result* out_dev, hipStream_t st, double* ei = nullptr,
+                          double* pi = nullptr, double* lcb = nullptr);
 hipError_t launch_scatter_posterior(const DevPtrs& P, const Layout& Lo, int64_t n_valid,
                                     const uint8_t* visited, double* mu, double* var, hipStream_t st);
 

@@ -47,6 +47,7 @@ struct FitArgs {
   double* alpha;
   double* z;
   void* Bpk;
+  int64_t* obs;  // the session's copy of the observations' candidate indices
   DevState* st;
 };
 
@@ -134,6 +135,7 @@ __device__ void fit_gather(const FitArgs& a, double* s_red, int* s_pos, int* s_b
       }
       s_pos[i] = pos[u];
       a.y[i] = v[u];
+      if (i < a.n) a.obs[i] = idx[u];
     }
   }
   __syncthreads();
@@ -957,7 +959,10 @@ __device__ void append_run(const FitArgs& a, unsigned char* s_raw) {
     a.Xo64[(size_t)n0 * kMaxD + t] = x;
     a.Xo32[(size_t)n0 * kMaxD + t] = (float)x;
   }
-  if (t == 0) a.y[n0] = a.y_in[n0];
+  if (t == 0) {
+    a.y[n0] = a.y_in[n0];
+    a.obs[n0] = a.obs_idx[n0];
+  }
   __syncthreads();
   // covariances of the new point to the old ones
   for (int i = t; i < n0; i += nt) {
@@ -1083,6 +1088,7 @@ inline FitArgs make_args(const DevPtrs& P, const Layout& Lo, const GpConst& g, c
   a.alpha = P.alpha;
   a.z = P.z;
   a.Bpk = P.Bpk;
+  a.obs = P.obs;
   a.st = P.st;
   return a;
 }

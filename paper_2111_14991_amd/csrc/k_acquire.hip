@@ -53,8 +53,12 @@ int64_t acquire_blocks(int64_t n_valid) {
 }
 
 hipError_t launch_acquire(const DevPtrs& P, const Layout& Lo, int64_t n_valid, const uint8_t* visited,
-                          const AcqArgs& acq, bo_acq_result* out_dev, hipStream_t st) {
-  const AcqKArgs a = make_acq_args(P, n_valid, visited, acq, out_dev);
+                          const AcqArgs& acq, bo_acq_result* out_dev, hipStream_t st, double* ei, double* pi,
+                          double* lcb) {
+  AcqKArgs a = make_acq_args(P, n_valid, visited, acq, out_dev);
+  a.vals[0] = ei;
+  a.vals[1] = pi;
+  a.vals[2] = lcb;
   const int grid = (int)acquire_blocks(n_valid);
   if (Lo.prec == BO_FP64)
     hipLaunchKernelGGL(k_acquire<false>, dim3(grid), dim3(kAcqThreads), 0, st, a);

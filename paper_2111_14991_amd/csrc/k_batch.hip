@@ -569,7 +569,7 @@ bo_status run_step(bo_batch* b, const bo_batch_config& cfg, const int64_t* const
     it.obs_idx = obs_idx[i];
     it.y = y[i];
     it.n = n[i];
-    it.visited = visited ? visited[i] : nullptr;
+    it.visited = (visited && visited[i]) ? visited[i] : it.s->P.vis;
     bo_status rc = acq_params_check(&params[i], &it.acq);
     if (rc != BO_OK) return rc;
     it.fit_kind = 0;

@@ -53,6 +53,29 @@ __global__ void k_state_clear(DevState* st, int full) {
   }
 }
 
+__global__ void k_fill_u8(uint8_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void k_fill_nan(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = __longlong_as_double(0x7ff8000000000000LL);
+}
+
+// One evaluation recorded in the session (Section III-D.2): the candidate is
+// marked evaluated; a valid evaluation is placed after the current fit's
+// observations, at position `at` of the session's observation list.
+__global__ void k_observe(uint8_t* vis, int64_t* obs, double* y, int64_t idx, double yv, int valid, int at) {
+  if (threadIdx.x == 0) {
+    vis[idx] = 1;
+    if (valid) {
+      obs[at] = idx;
+      y[at] = yv;
+    }
+  }
+}
+
 bo_status sync_state(bo_session* s) {
   HIP_TRY(hipMemcpyAsync(s->hstate, s->P.st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
@@ -104,12 +127,33 @@ bo_status enqueue_posterior(bo_session* s, const uint8_t* visited, const AcqArgs
   return BO_OK;
 }
 
-bo_status enqueue_step(bo_session* s, const uint8_t* visited, const AcqArgs& a, bo_acq_result* out_dev) {
+bo_status enqueue_step(bo_session* s, const uint8_t* visited, const AcqArgs& a, bo_acq_result* out_dev,
+                       double* ei = nullptr, double* pi = nullptr, double* lcb = nullptr) {
   bo_status rc = enqueue_posterior(s, visited, a);
   if (rc != BO_OK) return rc;
   MARK(s, 4);
-  HIP_TRY(launch_acquire(s->P, s->lo, s->n_valid, visited, a, out_dev, s->stream));
+  HIP_TRY(launch_acquire(s->P, s->lo, s->n_valid, visited, a, out_dev, s->stream, ei, pi, lcb));
   MARK(s, 5);
+  return BO_OK;
+}
+
+// Refit after one new observation at position n - 1 of (obs_idx, y): the
+// bordered extension of the current factor when it holds n - 1 points and
+// n <= kSmallFitMax, otherwise a whole fit.
+bo_status append_fit(bo_session* s, const int64_t* obs_idx, const double* y, int n) {
+  const bool bordered = s->have_fit && s->n == n - 1 && n <= kSmallFitMax;
+  s->n = n;
+  s->fit_attempt = 0;
+  s->large_fit = !bordered && n > kPlainSmallMax;
+  MARK(s, 0);
+  if (bordered)
+    HIP_TRY(launch_fit_append(s->P, s->lo, s->gp, obs_idx, y, n, s->stream));
+  else if (!s->large_fit)
+    HIP_TRY(launch_fit_small(s->P, s->lo, s->gp, obs_idx, y, n, s->stream));
+  else
+    HIP_TRY(launch_fit_large(s->P, s->lo, s->gp, obs_idx, y, n, 0, s->stream));
+  MARK(s, 1);
+  s->have_fit = 1;
   return BO_OK;
 }
 
@@ -133,6 +177,9 @@ bo_status set_candidates(bo_session* s, const int32_t* levels, const int64_t* ca
   hipLaunchKernelGGL(k_state_clear, dim3(1), dim3(64), 0, s->stream, s->P.st, 0);
   HIP_TRY(hipGetLastError());
   HIP_TRY(launch_grid_setup(s->P, s->lo, levels, d, cand, X, x_is_f32, invalid, N, s->stream));
+  hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)((s->lo.N_pad + 255) / 256)), dim3(256), 0, s->stream, s->P.vis,
+                     s->lo.N_pad);
+  HIP_TRY(hipGetLastError());
   bo_status rc = sync_state(s);
   if (rc != BO_OK) return rc;
   s->have_fit = 0;
@@ -143,6 +190,47 @@ bo_status set_candidates(bo_session* s, const int32_t* levels, const int64_t* ca
   s->n_valid = s->hstate->n_unmasked;
   s->have_cand = 1;
   if (n_valid) *n_valid = s->n_valid;
+  return BO_OK;
+}
+
+bo_status acquire_sync(bo_session* s, const uint8_t* visited, const bo_acq_params* params, bo_acq_result* out,
+                       double* ei, double* pi, double* lcb) {
+  bo_status rc = step_ready(s);
+  if (rc != BO_OK) return rc;
+  if (!out) return fail(BO_E_INVALID_ARG, "out is NULL");
+  if (!visited) visited = s->P.vis;
+  AcqArgs a;
+  rc = check_acq(params, &a);
+  if (rc != BO_OK) return rc;
+  if (s->n_valid == 0) {
+    bo_acq_result r{};
+    for (int k = 0; k < 3; ++k) {
+      r.idx[k] = -1;
+      r.score[k] = NAN;
+    }
+    r.status = BO_E_NO_CANDIDATE;
+    *out = r;
+    return fail(BO_E_NO_CANDIDATE, "every candidate is invalid");
+  }
+  for (double* v : {ei, pi, lcb})
+    if (v) {
+      hipLaunchKernelGGL(k_fill_nan, dim3((unsigned)((s->prob.N + 255) / 256)), dim3(256), 0, s->stream, v,
+                         s->prob.N);
+      HIP_TRY(hipGetLastError());
+    }
+  for (int round = 0; round < 2; ++round) {
+    rc = enqueue_step(s, visited, a, s->P.res, ei, pi, lcb);
+    if (rc != BO_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(s->hres, s->P.res, sizeof(bo_acq_result), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    if (!(s->hres->status == BO_E_NOT_PD && s->large_fit)) break;
+    bool retried;
+    rc = settle_fit(s, &retried);
+    if (rc != BO_OK) return rc;
+    if (!retried) break;
+  }
+  *out = *s->hres;
+  if (out->status != BO_OK) return fail((bo_status)out->status, "step finished with status %d", out->status);
   return BO_OK;
 }
 
@@ -240,6 +328,8 @@ bool make_layout(const bo_problem& p, Layout* L) {
   o.off_z = take(np * 8);
   o.off_Bpk = take(bpk_bytes(p.precision, (int)np));
   o.off_K0 = take(p.precision == BO_FP32 ? np * np * 8 : 0);
+  o.off_obs = take(np * 8);
+  o.off_vis = take(Np);
   o.total = off;
   *L = o;
   return true;
@@ -269,6 +359,8 @@ DevPtrs carve(const Layout& o, uint8_t* b) {
   P.z = (double*)(b + o.off_z);
   P.Bpk = b + o.off_Bpk;
   P.K0 = o.prec == BO_FP32 ? (double*)(b + o.off_K0) : nullptr;
+  P.obs = (int64_t*)(b + o.off_obs);
+  P.vis = b + o.off_vis;
   return P;
 }
 
@@ -389,20 +481,24 @@ bo_status bo_gp_append(bo_session* s, const int64_t* obs_idx, const double* y, i
   if (n < 1) return fail(BO_E_STATE, "a fit needs at least one observation (n = %d)", n);
   if (n > s->prob.n_max) return fail(BO_E_INVALID_ARG, "n = %d exceeds n_max = %d", n, s->prob.n_max);
   if (!obs_idx || !y) return fail(BO_E_INVALID_ARG, "obs_idx or y is NULL");
-  const bool bordered = s->have_fit && s->n == n - 1 && n <= kSmallFitMax;
-  s->n = n;
-  s->fit_attempt = 0;
-  s->large_fit = !bordered && n > kPlainSmallMax;
-  MARK(s, 0);
-  if (bordered)
-    HIP_TRY(launch_fit_append(s->P, s->lo, s->gp, obs_idx, y, n, s->stream));
-  else if (!s->large_fit)
-    HIP_TRY(launch_fit_small(s->P, s->lo, s->gp, obs_idx, y, n, s->stream));
-  else
-    HIP_TRY(launch_fit_large(s->P, s->lo, s->gp, obs_idx, y, n, 0, s->stream));
-  MARK(s, 1);
-  s->have_fit = 1;
-  return BO_OK;
+  return append_fit(s, obs_idx, y, n);
+}
+
+bo_status bo_observe(bo_session* s, int64_t idx, double y, int32_t valid) {
+  if (!s) return fail(BO_E_INVALID_ARG, "session is NULL");
+  if (!s->have_cand) return fail(BO_E_STATE, "no candidate set");
+  if (idx < 0 || idx >= s->prob.N) return fail(BO_E_INVALID_ARG, "idx %lld outside [0, N)", (long long)idx);
+  if (valid != 0 && valid != 1) return fail(BO_E_INVALID_ARG, "valid must be 0 or 1");
+  const int n_new = (s->have_fit ? s->n : 0) + 1;
+  if (valid) {
+    if (!std::isfinite(y)) return fail(BO_E_INVALID_ARG, "y is not finite");
+    if (n_new > s->prob.n_max) return fail(BO_E_INVALID_ARG, "n = %d exceeds n_max = %d", n_new, s->prob.n_max);
+  }
+  hipLaunchKernelGGL(k_observe, dim3(1), dim3(64), 0, s->stream, s->P.vis, s->P.obs, s->P.y, idx, y, valid,
+                     n_new - 1);
+  HIP_TRY(hipGetLastError());
+  if (!valid) return BO_OK;
+  return append_fit(s, s->P.obs, s->P.y, n_new);
 }
 
 bo_status bo_fit_read(bo_session* s, bo_fit_info* info, double* alpha, double* Linv) {
@@ -437,6 +533,7 @@ bo_status bo_fit_read(bo_session* s, bo_fit_info* info, double* alpha, double* L
 bo_status bo_posterior(bo_session* s, const uint8_t* visited, double* mu, double* var, double* var_mean) {
   bo_status rc = step_ready(s);
   if (rc != BO_OK) return rc;
+  if (!visited) visited = s->P.vis;
   if (s->n_valid == 0) return fail(BO_E_NO_CANDIDATE, "every candidate is invalid");
   AcqArgs a{0, 7u, 0.0, 0.0, 0.0};
   for (int round = 0; round < 2; ++round) {
@@ -457,36 +554,12 @@ bo_status bo_posterior(bo_session* s, const uint8_t* visited, double* mu, double
 }
 
 bo_status bo_acquire(bo_session* s, const uint8_t* visited, const bo_acq_params* params, bo_acq_result* out) {
-  bo_status rc = step_ready(s);
-  if (rc != BO_OK) return rc;
-  if (!out) return fail(BO_E_INVALID_ARG, "out is NULL");
-  AcqArgs a;
-  rc = check_acq(params, &a);
-  if (rc != BO_OK) return rc;
-  if (s->n_valid == 0) {
-    bo_acq_result r{};
-    for (int k = 0; k < 3; ++k) {
-      r.idx[k] = -1;
-      r.score[k] = NAN;
-    }
-    r.status = BO_E_NO_CANDIDATE;
-    *out = r;
-    return fail(BO_E_NO_CANDIDATE, "every candidate is invalid");
-  }
-  for (int round = 0; round < 2; ++round) {
-    rc = enqueue_step(s, visited, a, s->P.res);
-    if (rc != BO_OK) return rc;
-    HIP_TRY(hipMemcpyAsync(s->hres, s->P.res, sizeof(bo_acq_result), hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    if (!(s->hres->status == BO_E_NOT_PD && s->large_fit)) break;
-    bool retried;
-    rc = settle_fit(s, &retried);
-    if (rc != BO_OK) return rc;
-    if (!retried) break;
-  }
-  *out = *s->hres;
-  if (out->status != BO_OK) return fail((bo_status)out->status, "step finished with status %d", out->status);
-  return BO_OK;
+  return acquire_sync(s, visited, params, out, nullptr, nullptr, nullptr);
+}
+
+bo_status bo_acquire_values(bo_session* s, const uint8_t* visited, const bo_acq_params* params, double* ei,
+                            double* pi, double* lcb, bo_acq_result* out) {
+  return acquire_sync(s, visited, params, out, ei, pi, lcb);
 }
 
 bo_status bo_acquire_async(bo_session* s, const uint8_t* visited, const bo_acq_params* params,
@@ -498,6 +571,7 @@ bo_status bo_acquire_async(bo_session* s, const uint8_t* visited, const bo_acq_p
   rc = check_acq(params, &a);
   if (rc != BO_OK) return rc;
   if (s->n_valid == 0) return fail(BO_E_NO_CANDIDATE, "every candidate is invalid");
+  if (!visited) visited = s->P.vis;
   return enqueue_step(s, visited, a, out_dev);
 }
 

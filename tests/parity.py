@@ -23,10 +23,7 @@ def normwise_err(got, ref, scale):
 
 def acq_arrays(mu, var, f_best, lam, mask):
     """Reference acquisitions of every predicted candidate (oracle formulas)."""
-    A = np.full((mu.shape[0], 3), np.nan)
-    for c in np.flatnonzero(~mask):
-        A[c] = oracle.acquisitions(mu[c], var[c], f_best, lam)
-    return A
+    return oracle.acquisition_arrays(np.nan_to_num(mu), np.nan_to_num(var), mask, f_best, lam)
 
 
 def index_ok(g, o, A_ref, q, mask, tol, scale):
