@@ -244,6 +244,27 @@ bo_status bo_acquire_values(bo_session* s, const uint8_t* visited, const bo_acq_
 bo_status bo_acquire_async(bo_session* s, const uint8_t* visited, const bo_acq_params* params,
                            bo_acq_result* out_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture aside: this call synchronizes), e.g. tight serving loops or
+ * harnesses that forbid hipMalloc: one whole step with no session and no
+ * workspace.  Equivalent to bo_session_create + bo_set_candidates(X, x_is_f32,
+ * invalid) + bo_gp_fit(obs_idx, y, n) + bo_acquire(visited, params) on the
+ * same arguments, with the same kernels and the same result, but all device
+ * state lives in a static device array of 32 MiB that the library holds on
+ * each GPU it runs on until the process ends; the call allocates nothing
+ * (no hipMalloc, no pinned host memory, no host heap).  Arguments are those
+ * of the calls it replaces (device pointers X, invalid, visited, obs_idx, y;
+ * host prob, gp (NULL: defaults), params, out; stream as in
+ * bo_session_create).  visited NULL means nothing evaluated yet.
+ * BO_E_WORKSPACE when the problem's device state (bo_workspace_query of prob)
+ * exceeds the 32 MiB.  Every call on one GPU uses that GPU's single array:
+ * calls that overlap on one GPU (two host threads, or two streams) race and
+ * must be serialized by the caller.  Synchronizing; returns out->status as
+ * bo_acquire does. */
+bo_status bo_step_noalloc(const bo_problem* prob, const bo_gp_params* gp, const void* X, int32_t x_is_f32,
+                          const uint8_t* invalid, const uint8_t* visited, const int64_t* obs_idx, const double* y,
+                          int32_t n, const bo_acq_params* params, bo_acq_result* out, void* stream);
+
 /* Phase timing.  With timing enabled the library records HIP events on the
  * session stream around its own launches: the fit (bo_gp_fit), the posterior
  * kernel and the acquisition kernel (bo_posterior / bo_acquire).

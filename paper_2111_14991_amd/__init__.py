@@ -102,6 +102,8 @@ _SIGS = {
     "bo_acquire_values": (C.c_int, [_VP, _U8P, C.POINTER(bo_acq_params), _DP, _DP, _DP,
                                     C.POINTER(bo_acq_result)]),
     "bo_acquire_async": (C.c_int, [_VP, _U8P, C.POINTER(bo_acq_params), _VP]),
+    "bo_step_noalloc": (C.c_int, [C.POINTER(bo_problem), C.POINTER(bo_gp_params), _VP, C.c_int32, _U8P, _U8P,
+                                  _I64P, _DP, C.c_int32, C.POINTER(bo_acq_params), C.POINTER(bo_acq_result), _VP]),
     "bo_set_timing": (C.c_int, [_VP, C.c_int32]),
     "bo_get_timing": (C.c_int, [_VP, C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "bo_batch_workspace_query": (C.c_int, [C.c_int32, C.POINTER(C.c_size_t)]),
@@ -394,6 +396,34 @@ class Session:
         a = (acq or AcqParams(mode=0)).c()
         _check(lib().bo_acquire_async(self.h, _ptr(visited), C.byref(a), out_dev.data_ptr()),
                "bo_acquire_async")
+
+
+def bo_step_noalloc(X, obs_idx, y, precision="fp64", invalid=None, visited=None, gp: Optional[GpParams] = None,
+                    acq: Optional[AcqParams] = None, n_max: Optional[int] = None, stream=None, check=True):
+    """One whole step with no session and no workspace (bo_step_noalloc): X is
+    an N x d device tensor of normalized coordinates (float64, or float32),
+    invalid / visited device uint8[N] or None, obs_idx / y the observations.
+    Runs on the current torch stream of X's device unless `stream` is given."""
+    torch = _torch()
+    dev = X.device
+    f32 = 1 if X.dtype == torch.float32 else 0
+    Xd = X.contiguous() if f32 else X.to(torch.float64).contiguous()
+    oi = _dev(obs_idx, torch.int64, torch, dev)
+    yy = _dev(y, torch.float64, torch, dev)
+    inv = _dev(invalid, torch.uint8, torch, dev)
+    vis = _dev(visited, torch.uint8, torch, dev)
+    n = int(oi.shape[0])
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    prob = bo_problem(int(Xd.shape[0]), int(Xd.shape[1]), int(n_max or n), prec, 0)
+    g = (gp or GpParams()).c()
+    a = (acq or AcqParams(mode=0)).c()
+    st = torch.cuda.current_stream(dev) if stream is None else stream
+    r = bo_acq_result()
+    rc = lib().bo_step_noalloc(C.byref(prob), C.byref(g), _ptr(Xd), f32, _ptr(inv), _ptr(vis), _ptr(oi), _ptr(yy),
+                               n, C.byref(a), C.byref(r), st.cuda_stream)
+    if check and rc != BO_OK:
+        raise BOError(rc, "bo_step_noalloc", last_error())
+    return _result(r)
 
 
 class Batch:

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -17,6 +18,14 @@ using namespace bo;
 namespace bo {
 int64_t acquire_blocks(int64_t n_valid);
 }
+
+// Device memory of bo_step_noalloc: one copy per GPU, held until the process
+// ends.  Host code never passes the array's name to a kernel or a copy (on the
+// host it is only a stand-in for the symbol); it uses the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 
 
 namespace {
@@ -98,6 +107,39 @@ bo_status settle_fit(bo_session* s, bool* retried) {
 }
 
 bo_status check_acq(const bo_acq_params* a, AcqArgs* out) { return acq_params_check(a, out); }
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices];
+
+// Address of the current device's scratch array, looked up once per device.
+bo_status scratch_of_current_device(uint8_t** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(BO_E_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kScratchDevices) return fail(BO_E_HIP, "device %d beyond the %d supported", dev, kScratchDevices);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(BO_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (uint8_t*)g_scratch_ptr[dev];
+  return BO_OK;
+}
+
+// GP parameters (NULL: the defaults) checked into *g.
+bo_status gp_check(const bo_gp_params* gp, bo_gp_params* g) {
+  *g = bo_gp_params{5, 7, 1.0, 1.0, 1e-6};
+  if (gp) *g = *gp;
+  if (g->nu2 != 3 && g->nu2 != 5) return fail(BO_E_INVALID_ARG, "nu2 must be 3 or 5");
+  if (!(g->lengthscale > 0.0) || !std::isfinite(g->lengthscale)) return fail(BO_E_INVALID_ARG, "lengthscale");
+  if (!(g->amp > 0.0) || !std::isfinite(g->amp)) return fail(BO_E_INVALID_ARG, "amp");
+  if (!(g->noise >= 0.0) || !std::isfinite(g->noise)) return fail(BO_E_INVALID_ARG, "noise");
+  if (g->jitter_tries < 1 || g->jitter_tries > 20) return fail(BO_E_INVALID_ARG, "jitter_tries must be 1..20");
+  return BO_OK;
+}
 
 bo_status step_ready(bo_session* s) {
   if (!s) return fail(BO_E_INVALID_ARG, "session is NULL");
@@ -387,13 +429,9 @@ bo_status bo_session_create(bo_session** out, const bo_problem* prob, const bo_g
   if (!out) return fail(BO_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!problem_ok(prob)) return fail(BO_E_INVALID_ARG, "problem outside limits");
-  bo_gp_params g = {5, 7, 1.0, 1.0, 1e-6};
-  if (gp) g = *gp;
-  if (g.nu2 != 3 && g.nu2 != 5) return fail(BO_E_INVALID_ARG, "nu2 must be 3 or 5");
-  if (!(g.lengthscale > 0.0) || !std::isfinite(g.lengthscale)) return fail(BO_E_INVALID_ARG, "lengthscale");
-  if (!(g.amp > 0.0) || !std::isfinite(g.amp)) return fail(BO_E_INVALID_ARG, "amp");
-  if (!(g.noise >= 0.0) || !std::isfinite(g.noise)) return fail(BO_E_INVALID_ARG, "noise");
-  if (g.jitter_tries < 1 || g.jitter_tries > 20) return fail(BO_E_INVALID_ARG, "jitter_tries must be 1..20");
+  bo_gp_params g;
+  bo_status grc = gp_check(gp, &g);
+  if (grc != BO_OK) return grc;
   Layout L;
   make_layout(*prob, &L);
   if (!workspace || ((uintptr_t)workspace & 255u)) return fail(BO_E_WORKSPACE, "workspace NULL or not 256-aligned");
@@ -600,6 +638,54 @@ bo_status bo_get_timing(bo_session* s, float* fit_ms, float* posterior_ms, float
     if (s->ev_have[k]) HIP_TRY(hipEventElapsedTime(outs[k], s->ev[2 * k], s->ev[2 * k + 1]));
   }
   return BO_OK;
+}
+
+bo_status bo_step_noalloc(const bo_problem* prob, const bo_gp_params* gp, const void* X, int32_t x_is_f32,
+                          const uint8_t* invalid, const uint8_t* visited, const int64_t* obs_idx, const double* y,
+                          int32_t n, const bo_acq_params* params, bo_acq_result* out, void* stream) {
+  if (!out) return fail(BO_E_INVALID_ARG, "out is NULL");
+  if (!problem_ok(prob)) return fail(BO_E_INVALID_ARG, "problem outside limits");
+  if (!X) return fail(BO_E_INVALID_ARG, "X is NULL");
+  if (x_is_f32 != 0 && x_is_f32 != 1) return fail(BO_E_INVALID_ARG, "x_is_f32 must be 0 or 1");
+  if (n < 1) return fail(BO_E_STATE, "a fit needs at least one observation (n = %d)", n);
+  if (n > prob->n_max) return fail(BO_E_INVALID_ARG, "n = %d exceeds n_max = %d", n, prob->n_max);
+  if (!obs_idx || !y) return fail(BO_E_INVALID_ARG, "obs_idx or y is NULL");
+  bo_gp_params g;
+  bo_status rc = gp_check(gp, &g);
+  if (rc != BO_OK) return rc;
+  AcqArgs a;
+  rc = check_acq(params, &a);
+  if (rc != BO_OK) return rc;
+  Layout L;
+  make_layout(*prob, &L);
+  if (L.total > kScratchBytes)
+    return fail(BO_E_WORKSPACE, "problem needs %zu bytes of device memory; the static scratch holds %zu", L.total,
+                kScratchBytes);
+  uint8_t* ws = nullptr;
+  rc = scratch_of_current_device(&ws);
+  if (rc != BO_OK) return rc;
+  // a session on the stack over the scratch array; its host-side copies of
+  // the result and the state are stack variables (pageable memory)
+  bo_acq_result hres{};
+  DevState hstate{};
+  bo_session s{};
+  s.prob = *prob;
+  s.gp = GpConst{g.nu2, g.jitter_tries, g.lengthscale, g.amp, g.noise};
+  s.lo = L;
+  s.ws = ws;
+  s.ws_bytes = kScratchBytes;
+  s.P = carve(L, ws);
+  s.stream = (hipStream_t)stream;
+  s.hres = &hres;
+  s.hstate = &hstate;
+  // the array keeps the previous call's contents: start from a cleared state
+  hipLaunchKernelGGL(k_state_clear, dim3(1), dim3(64), 0, s.stream, s.P.st, 1);
+  HIP_TRY(hipGetLastError());
+  rc = set_candidates(&s, nullptr, nullptr, X, x_is_f32, invalid, nullptr);
+  if (rc != BO_OK) return rc;
+  rc = bo_gp_fit(&s, obs_idx, y, n);
+  if (rc != BO_OK) return rc;
+  return acquire_sync(&s, visited, params, out, nullptr, nullptr, nullptr);
 }
 
 }  // extern "C"
