@@ -37,6 +37,57 @@ __device__ __forceinline__ float matern32_r2(int nu2, float r2, float inv_l) {
   return (1.0f + rho) * e;
 }
 
+// Augmented FP16 coordinates of the BF16X3 posterior's distance products.
+// With c = candidate, o = observation, S = kAugScale, T = kAugPair, the rows
+//   c: S c[0..d-1],   T,  S^2|c|^2/T, T,  (.)_3
+//   o: -2S o[0..d-1], S^2|o|^2/T, T, (.)_3, T
+// multiply to S^2 (|c|^2 + |o|^2 - 2 c.o) = S^2 r^2.  Each entry is held as an
+// FP16 high part and an FP16 remainder; the squared norms take a third FP16
+// part (subscript 3) in the extra slot, so that the three products
+// high*high + high*low + low*high of the matrix cores reproduce each norm to
+// about 2^-33 of its size.  The scale keeps the remainders of coordinates in
+// [0, 1] in the normal FP16 range (a remainder that would be subnormal is
+// below 2^-14 / S of the coordinate), so that no significant part is lost to
+// a flush of subnormal inputs; S^2|c|^2/T stays below 2^12 for d <= 16.
+// w16 (16 or 32) entries per part; the row is hi[w16], lo[w16].
+constexpr double kAugScale = 1024.0;
+constexpr double kAugPair = 4096.0;
+
+__device__ __forceinline__ void aug16_row(const double* x, int d, bool obs, uint16_t* row, int w16) {
+  double nrm = 0.0;
+  for (int j = 0; j < d; ++j) nrm += x[j] * x[j];
+  nrm *= kAugScale * kAugScale / kAugPair;
+  const _Float16 n1 = (_Float16)nrm;
+  const _Float16 n2 = (_Float16)(nrm - (double)n1);
+  const _Float16 n3 = (_Float16)(nrm - (double)n1 - (double)n2);
+  _Float16* hi = reinterpret_cast<_Float16*>(row);
+  _Float16* lo = hi + w16;
+  for (int j = 0; j < w16; ++j) {
+    hi[j] = (_Float16)0.0f;
+    lo[j] = (_Float16)0.0f;
+  }
+  for (int j = 0; j < d; ++j) {
+    const double v = (obs ? -2.0 : 1.0) * kAugScale * x[j];
+    const _Float16 h = (_Float16)v;
+    hi[j] = h;
+    lo[j] = (_Float16)(v - (double)h);
+  }
+  const _Float16 pair = (_Float16)kAugPair;
+  if (obs) {
+    hi[d] = n1;
+    lo[d] = n2;
+    hi[d + 1] = pair;
+    hi[d + 2] = n3;
+    hi[d + 3] = pair;
+  } else {
+    hi[d] = pair;
+    hi[d + 1] = n1;
+    lo[d + 1] = n2;
+    hi[d + 2] = pair;
+    hi[d + 3] = n3;
+  }
+}
+
 // Diagonal addition of jitter attempt t: the noise first, then tenfold steps
 // from max(noise, 1e-10 amp).
 __device__ __host__ __forceinline__ double jitter_of(double noise, double amp, int t) {

@@ -63,7 +63,7 @@ struct DevPtrs {
   DevState* st;
   bo_acq_result* res;
   double* X64;        // [d][N_pad] normalized coordinates (SoA)
-  float* X32;         // [d][N_pad] (BF16X3 only)
+  uint16_t* Xc16;     // [N_pad][2][w16] augmented FP16 candidate coordinates (BF16X3 only)
   int32_t* orig;      // [N_pad] original index of compacted candidate, -1 pad
   int32_t* inv_map;   // [N] compacted position or -1 when invalid
   int32_t* blk;       // block counts / offsets for compaction
@@ -72,7 +72,7 @@ struct DevPtrs {
   VarSlot* vslots;
   AcqSlot* aslots;
   double* Xo64;       // [n_max_pad][kMaxD]
-  float* Xo32;        // [n_max_pad][kMaxD]
+  uint16_t* Xo16;     // [n_max_pad][2][w16] augmented FP16 observation coordinates (BF16X3 only)
   double* y;          // [n_max_pad]
   double* A;          // [n_max_pad^2] working matrix
   double* L;          // [n_max_pad^2]
@@ -88,12 +88,16 @@ struct DevPtrs {
 
 struct Layout {
   int64_t N, N_pad;
-  int d, n_max, n_max_pad, prec;
-  size_t off_st, off_res, off_X64, off_X32, off_orig, off_inv, off_blk, off_mu, off_var,
-      off_vslots, off_aslots, off_Xo64, off_Xo32, off_y, off_A, off_L, off_Dinv, off_Linv,
+  int d, n_max, n_max_pad, prec, w16;
+  size_t off_st, off_res, off_X64, off_Xc16, off_orig, off_inv, off_blk, off_mu, off_var,
+      off_vslots, off_aslots, off_Xo64, off_Xo16, off_y, off_A, off_L, off_Dinv, off_Linv,
       off_alpha, off_z, off_Bpk, off_K0, off_obs, off_vis, total;
   int64_t n_vslots, n_aslots;
 };
+
+// Entries per part of a row of augmented FP16 coordinates (BF16X3 distance
+// products): d coordinates and four norm slots, in one or two 16-wide k-steps.
+__host__ __device__ inline int aug16_width(int d) { return d + 4 <= 16 ? 16 : 32; }
 
 // Pad of the observation dimension used by every kernel for a fit of n points.
 inline int n_pad_of(int n) { return (int)round_up(n < 1 ? 1 : n, 64); }

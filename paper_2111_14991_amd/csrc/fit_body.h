@@ -37,7 +37,8 @@ struct FitArgs {
   const int32_t* inv_map;
   const double* X64;
   double* Xo64;
-  float* Xo32;
+  uint16_t* Xo16;  // augmented FP16 observation coordinates (BF16X3 only), rows of 2 * w16
+  int w16;
   double* y;
   double* A;     // working matrix, later the running right-hand side R of the inverse
   double* L;
@@ -148,10 +149,8 @@ __device__ void fit_gather(const FitArgs& a, double* s_red, int* s_pos, int* s_b
 #pragma unroll
     for (int j = 0; j < kMaxD; ++j) x[j] = (live && j < a.d) ? a.X64[(int64_t)j * a.N_pad + pos] : 0.0;
 #pragma unroll
-    for (int j = 0; j < kMaxD; ++j) {
-      a.Xo64[(size_t)i * kMaxD + j] = x[j];
-      a.Xo32[(size_t)i * kMaxD + j] = (float)x[j];
-    }
+    for (int j = 0; j < kMaxD; ++j) a.Xo64[(size_t)i * kMaxD + j] = x[j];
+    if (a.Xo16) aug16_row(x, a.d, true, a.Xo16 + (size_t)i * 2 * a.w16, a.w16);
   }
   // fixed-order tree reductions of the sum and the minimum
   s_red[t] = yv;
@@ -957,7 +956,11 @@ __device__ void append_run(const FitArgs& a, unsigned char* s_raw) {
   if (t < kMaxD) {
     const double x = t < a.d ? a.X64[(int64_t)t * a.N_pad + s_pos0] : 0.0;
     a.Xo64[(size_t)n0 * kMaxD + t] = x;
-    a.Xo32[(size_t)n0 * kMaxD + t] = (float)x;
+  }
+  if (a.Xo16 && t == 0) {
+    double x[kMaxD];
+    for (int j = 0; j < a.d; ++j) x[j] = a.X64[(int64_t)j * a.N_pad + s_pos0];
+    aug16_row(x, a.d, true, a.Xo16 + (size_t)n0 * 2 * a.w16, a.w16);
   }
   if (t == 0) {
     a.y[n0] = a.y_in[n0];
@@ -1078,7 +1081,8 @@ inline FitArgs make_args(const DevPtrs& P, const Layout& Lo, const GpConst& g, c
   a.inv_map = P.inv_map;
   a.X64 = P.X64;
   a.Xo64 = P.Xo64;
-  a.Xo32 = P.Xo32;
+  a.Xo16 = P.Xo16;
+  a.w16 = Lo.w16;
   a.y = P.y;
   a.A = P.A;
   a.L = P.L;

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_scan(int nblk, int32_t*
 __global__ __launch_bounds__(kSetupThreads) void k_setup_scatter(int64_t N, int64_t N_pad, GridArgs ga,
                                                                  const int64_t* cand, const void* Xin,
                                                                  const uint8_t* invalid, const int32_t* blk,
-                                                                 const DevState* st, double* X64, float* X32,
+                                                                 const DevState* st, double* X64,
                                                                  int32_t* orig, int32_t* inv_map) {
   __shared__ int32_t s_wave[kSetupThreads / 64];
   const int64_t c = (int64_t)blockIdx.x * kSetupThreads + threadIdx.x;
@@ -92,14 +92,12 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_scatter(int64_t N, int6
           g /= k;
           const double x = k > 1 ? (double)i / (double)(k - 1) : 0.0;
           X64[(int64_t)j * N_pad + pos] = x;
-          if (X32) X32[(int64_t)j * N_pad + pos] = (float)x;
         }
       } else {
         for (int j = 0; j < ga.d; ++j) {
           const double x = ga.from_coords == 1 ? ((const double*)Xin)[c * ga.d + j]
                                                : (double)((const float*)Xin)[c * ga.d + j];
           X64[(int64_t)j * N_pad + pos] = x;
-          if (X32) X32[(int64_t)j * N_pad + pos] = (float)x;
         }
       }
     } else {
@@ -110,11 +108,19 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_scatter(int64_t N, int6
   const int64_t nv = st->n_unmasked;
   if (c >= nv && c < N_pad) {
     orig[c] = -1;
-    for (int j = 0; j < ga.d; ++j) {
-      X64[(int64_t)j * N_pad + c] = 0.0;
-      if (X32) X32[(int64_t)j * N_pad + c] = 0.f;
-    }
+    for (int j = 0; j < ga.d; ++j) X64[(int64_t)j * N_pad + c] = 0.0;
   }
+}
+
+// Augmented FP16 coordinates of every compacted candidate (padding rows
+// included) for the BF16X3 distance products.
+__global__ __launch_bounds__(kSetupThreads) void k_setup_aug16(int64_t N_pad, int d, int w16, const double* X64,
+                                                               uint16_t* Xc16) {
+  const int64_t c = (int64_t)blockIdx.x * kSetupThreads + threadIdx.x;
+  if (c >= N_pad) return;
+  double x[kMaxD];
+  for (int j = 0; j < d; ++j) x[j] = X64[(int64_t)j * N_pad + c];
+  aug16_row(x, d, false, Xc16 + c * 2 * w16, w16);
 }
 
 }  // namespace
@@ -138,7 +144,10 @@ hipError_t launch_grid_setup(const DevPtrs& P, const Layout& Lo, const int32_t* 
   hipLaunchKernelGGL(k_setup_count, dim3(nblk), dim3(kSetupThreads), 0, st, N, ga, cand, invalid, P.blk, P.st);
   hipLaunchKernelGGL(k_setup_scan, dim3(1), dim3(kSetupThreads), 0, st, nblk, P.blk, P.st);
   hipLaunchKernelGGL(k_setup_scatter, dim3(nblk_pad), dim3(kSetupThreads), 0, st, N, Lo.N_pad, ga, cand, Xin,
-                     invalid, P.blk, P.st, P.X64, P.X32, P.orig, P.inv_map);
+                     invalid, P.blk, P.st, P.X64, P.orig, P.inv_map);
+  if (P.Xc16)
+    hipLaunchKernelGGL(k_setup_aug16, dim3((unsigned)((Lo.N_pad + kSetupThreads - 1) / kSetupThreads)),
+                       dim3(kSetupThreads), 0, st, Lo.N_pad, d, Lo.w16, P.X64, P.Xc16);
   return hipGetLastError();
 }
 

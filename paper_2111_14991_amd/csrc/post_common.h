@@ -13,11 +13,12 @@ struct PostArgs {
   double inv_l, amp;
   int64_t n_valid, N_pad;
   const double* X64;
-  const float* X32;
+  const uint16_t* Xc16;  // augmented FP16 candidate coordinates, rows of 2 * w16 (BF16X3)
   const int32_t* orig;
   const uint8_t* visited;
   const double* Xo64;
-  const float* Xo32;
+  const uint16_t* Xo16;  // augmented FP16 observation coordinates, rows of 2 * w16 (BF16X3)
+  int w16;
   const double* alpha;
   const void* Bpk;
   const double* K0;
@@ -889,11 +890,12 @@ inline PostArgs make_post_args(const DevPtrs& P, const Layout& Lo, const GpConst
   a.n_valid = n_valid;
   a.N_pad = Lo.N_pad;
   a.X64 = P.X64;
-  a.X32 = P.X32;
+  a.Xc16 = P.Xc16;
   a.orig = P.orig;
   a.visited = visited;
   a.Xo64 = P.Xo64;
-  a.Xo32 = P.Xo32;
+  a.Xo16 = P.Xo16;
+  a.w16 = Lo.w16;
   a.alpha = P.alpha;
   a.Bpk = P.Bpk;
   a.K0 = P.K0;

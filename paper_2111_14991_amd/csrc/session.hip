@@ -336,6 +336,7 @@ bool make_layout(const bo_problem& p, Layout* L) {
   o.n_max = p.n_max;
   o.n_max_pad = n_pad_of(p.n_max);
   o.prec = p.precision;
+  o.w16 = aug16_width(p.d);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
@@ -351,7 +352,7 @@ bool make_layout(const bo_problem& p, Layout* L) {
   o.off_st = take(sizeof(DevState));
   o.off_res = take(sizeof(bo_acq_result));
   o.off_X64 = take((size_t)o.d * Np * 8);
-  o.off_X32 = take(p.precision == BO_BF16X3 ? (size_t)o.d * Np * 4 : 0);
+  o.off_Xc16 = take(p.precision == BO_BF16X3 ? Np * 2 * o.w16 * 2 : 0);
   o.off_orig = take(Np * 4);
   o.off_inv = take((size_t)o.N * 4);
   o.off_blk = take(((Np > (size_t)o.N ? Np : (size_t)o.N) / 1024 + 2) * 4);
@@ -360,7 +361,7 @@ bool make_layout(const bo_problem& p, Layout* L) {
   o.off_vslots = take((size_t)o.n_vslots * sizeof(VarSlot));
   o.off_aslots = take((size_t)o.n_aslots * sizeof(AcqSlot));
   o.off_Xo64 = take(np * kMaxD * 8);
-  o.off_Xo32 = take(np * kMaxD * 4);
+  o.off_Xo16 = take(p.precision == BO_BF16X3 ? np * 2 * o.w16 * 2 : 0);
   o.off_y = take(np * 8);
   o.off_A = take(np * np * 8);
   o.off_L = take(np * np * 8);
@@ -382,7 +383,7 @@ DevPtrs carve(const Layout& o, uint8_t* b) {
   P.st = (DevState*)(b + o.off_st);
   P.res = (bo_acq_result*)(b + o.off_res);
   P.X64 = (double*)(b + o.off_X64);
-  P.X32 = o.prec == BO_BF16X3 ? (float*)(b + o.off_X32) : nullptr;
+  P.Xc16 = o.prec == BO_BF16X3 ? (uint16_t*)(b + o.off_Xc16) : nullptr;
   P.orig = (int32_t*)(b + o.off_orig);
   P.inv_map = (int32_t*)(b + o.off_inv);
   P.blk = (int32_t*)(b + o.off_blk);
@@ -391,7 +392,7 @@ DevPtrs carve(const Layout& o, uint8_t* b) {
   P.vslots = (VarSlot*)(b + o.off_vslots);
   P.aslots = (AcqSlot*)(b + o.off_aslots);
   P.Xo64 = (double*)(b + o.off_Xo64);
-  P.Xo32 = (float*)(b + o.off_Xo32);
+  P.Xo16 = o.prec == BO_BF16X3 ? (uint16_t*)(b + o.off_Xo16) : nullptr;
   P.y = (double*)(b + o.off_y);
   P.A = (double*)(b + o.off_A);
   P.L = (double*)(b + o.off_L);

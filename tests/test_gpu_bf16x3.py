@@ -77,6 +77,13 @@ def test_bf16x3_mid_size_parity(bo, n):
     bf16x3_parity(bo, W.make_session(20 + n, (6, 6, 6, 6, 6), n, invalid_frac=0.3))
 
 
+@pytest.mark.parametrize("d,n", [(12, 150), (14, 200), (16, 70)])
+def test_bf16x3_wide_parity(bo, d, n):
+    # d + 4 > 16 takes the distance products over two k-steps (d = 14, 16);
+    # d = 12 is the widest space with one
+    bf16x3_parity(bo, W.make_session(90 + d, (2,) * d, n, invalid_frac=0.2))
+
+
 def test_bf16x3_full_size(bo):
     """The 1M-candidate step (4^10 grid, 30% invalid, n = 1000) in the launch
     configuration the benchmark times, against one whole FP64 oracle step:
