@@ -238,9 +238,8 @@ bo_status bo_acquire_values(bo_session* s, const uint8_t* visited, const bo_acq_
                             double* pi, double* lcb, bo_acq_result* out);
 
 /* Same as bo_acquire without waiting: *out_dev (device) is written on the
- * session stream.  A fit of more than 128 observations by bo_gp_fit runs on
- * the multi-workgroup path, whose jitter escalation is driven by the host:
- * it is not retried here, and out_dev->status reports BO_E_NOT_PD instead. */
+ * session stream.  The jitter schedule of the fit is escalated on the device
+ * (every fit size), so the result equals bo_acquire's. */
 bo_status bo_acquire_async(bo_session* s, const uint8_t* visited, const bo_acq_params* params,
                            bo_acq_result* out_dev);
 

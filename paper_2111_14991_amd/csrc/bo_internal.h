@@ -26,7 +26,7 @@ struct DevState {
   int32_t status;       // fit status (BO_OK or an error code)
   int32_t attempt;      // accepted jitter attempt, or the failed one
   int32_t n;            // observations in the current fit
-  int32_t need_retry;   // large fit: pivot failed at `attempt`, host retries
+  int32_t need_retry;   // unused (kept 0)
   double mean_y, f_best, jitter;
   double lambda, var_mean;
   double min_piv;       // smallest accepted Cholesky pivot of the current factor
@@ -34,8 +34,13 @@ struct DevState {
   int32_t post_status;  // posterior / lambda status
   int32_t pad0;
   uint32_t ticket_post, ticket_acq, ticket_fit, pad1;
-  int32_t fail_flag;    // large fit: pivot failure in the current attempt
+  int32_t fail_flag;    // unused (kept 0)
   int32_t pad2;
+  // grid-wide barriers of the persistent large fit: cumulative arrivals, the
+  // last barrier released, a flag that ends every wait (a spin limit hit),
+  // and the phase of the current attempt in which a pivot failed (0: tile 0,
+  // k + 1: the look-ahead of step k; 0xffffffff: none)
+  uint32_t gs_arrive, gs_release, gs_abort, fail_at;
 };
 
 // Per-workgroup partial of the mean posterior variance.

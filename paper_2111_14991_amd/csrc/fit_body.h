@@ -12,9 +12,10 @@
 //        block row k of the inverse, X_kj = L_kk^-1 R_kj (j < k), X_kk;
 //   B_k: trailing update A_ij -= L_ik L_jk^T (k < j <= i) and the running
 //        right-hand side of the inverse R_ij -= L_ik X_kj (i > k >= j).
-// n <= 256: one workgroup (two teams) runs every step, jitter retries
-// included.  n > 256: one launch per A_k / B_k with one team per tile; the
-// host retries the jitter schedule after a pivot failure.
+// Small fits: one workgroup (two teams) runs every step, jitter retries
+// included.  Large fits: one launch of co-resident workgroups with grid-wide
+// barriers between the steps and a look-ahead of the next diagonal tile,
+// jitter retries included (k_fit.hip).
 #pragma once
 #include <type_traits>
 #include "bo_internal.h"
@@ -173,6 +174,10 @@ __device__ void fit_gather(const FitArgs& a, double* s_red, int* s_pos, int* s_b
     st->fail_flag = 0;
     st->attempt = 0;
     st->min_piv = INFINITY;
+    st->gs_arrive = 0;
+    st->gs_release = 0;
+    st->gs_abort = 0;
+    st->fail_at = 0xffffffffu;
   }
   __syncthreads();
 }

@@ -581,7 +581,6 @@ bo_status run_step(bo_batch* b, const bo_batch_config& cfg, const int64_t* const
   for (int i = 0; i < count; ++i) {
     bo_session* s = b->ses[i];
     s->n = n[i];
-    s->fit_attempt = 0;
     s->large_fit = 0;
     s->have_fit = 1;
   }

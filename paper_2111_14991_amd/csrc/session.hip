@@ -91,21 +91,6 @@ bo_status sync_state(bo_session* s) {
   return BO_OK;
 }
 
-// Large fits retry the jitter schedule from the host after a pivot failure.
-bo_status settle_fit(bo_session* s, bool* retried) {
-  *retried = false;
-  bo_status rc = sync_state(s);
-  if (rc != BO_OK) return rc;
-  while (s->hstate->status == BO_E_NOT_PD && s->hstate->need_retry && s->large_fit) {
-    s->fit_attempt += 1;
-    HIP_TRY(launch_fit_large(s->P, s->lo, s->gp, nullptr, nullptr, s->n, s->fit_attempt, s->stream));
-    rc = sync_state(s);
-    if (rc != BO_OK) return rc;
-    *retried = true;
-  }
-  return BO_OK;
-}
-
 bo_status check_acq(const bo_acq_params* a, AcqArgs* out) { return acq_params_check(a, out); }
 
 std::mutex g_scratch_mu;
@@ -185,7 +170,6 @@ bo_status enqueue_step(bo_session* s, const uint8_t* visited, const AcqArgs& a, 
 bo_status append_fit(bo_session* s, const int64_t* obs_idx, const double* y, int n) {
   const bool bordered = s->have_fit && s->n == n - 1 && n <= kSmallFitMax;
   s->n = n;
-  s->fit_attempt = 0;
   s->large_fit = !bordered && n > kPlainSmallMax;
   MARK(s, 0);
   if (bordered)
@@ -260,17 +244,10 @@ bo_status acquire_sync(bo_session* s, const uint8_t* visited, const bo_acq_param
                          s->prob.N);
       HIP_TRY(hipGetLastError());
     }
-  for (int round = 0; round < 2; ++round) {
-    rc = enqueue_step(s, visited, a, s->P.res, ei, pi, lcb);
-    if (rc != BO_OK) return rc;
-    HIP_TRY(hipMemcpyAsync(s->hres, s->P.res, sizeof(bo_acq_result), hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
-    if (!(s->hres->status == BO_E_NOT_PD && s->large_fit)) break;
-    bool retried;
-    rc = settle_fit(s, &retried);
-    if (rc != BO_OK) return rc;
-    if (!retried) break;
-  }
+  rc = enqueue_step(s, visited, a, s->P.res, ei, pi, lcb);
+  if (rc != BO_OK) return rc;
+  HIP_TRY(hipMemcpyAsync(s->hres, s->P.res, sizeof(bo_acq_result), hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
   *out = *s->hres;
   if (out->status != BO_OK) return fail((bo_status)out->status, "step finished with status %d", out->status);
   return BO_OK;
@@ -501,7 +478,6 @@ bo_status bo_gp_fit(bo_session* s, const int64_t* obs_idx, const double* y, int3
   if (n > s->prob.n_max) return fail(BO_E_INVALID_ARG, "n = %d exceeds n_max = %d", n, s->prob.n_max);
   if (!obs_idx || !y) return fail(BO_E_INVALID_ARG, "obs_idx or y is NULL");
   s->n = n;
-  s->fit_attempt = 0;
   // one session: the multi-workgroup fit is faster above kPlainSmallMax
   s->large_fit = n > kPlainSmallMax;
   MARK(s, 0);
@@ -543,8 +519,7 @@ bo_status bo_observe(bo_session* s, int64_t idx, double y, int32_t valid) {
 bo_status bo_fit_read(bo_session* s, bo_fit_info* info, double* alpha, double* Linv) {
   if (!s) return fail(BO_E_INVALID_ARG, "session is NULL");
   if (!s->have_fit) return fail(BO_E_STATE, "no fit");
-  bool retried;
-  bo_status rc = settle_fit(s, &retried);
+  bo_status rc = sync_state(s);
   if (rc != BO_OK) return rc;
   const DevState& h = *s->hstate;
   if (info) {
@@ -575,16 +550,12 @@ bo_status bo_posterior(bo_session* s, const uint8_t* visited, double* mu, double
   if (!visited) visited = s->P.vis;
   if (s->n_valid == 0) return fail(BO_E_NO_CANDIDATE, "every candidate is invalid");
   AcqArgs a{0, 7u, 0.0, 0.0, 0.0};
-  for (int round = 0; round < 2; ++round) {
-    rc = enqueue_posterior(s, visited, a);
-    if (rc != BO_OK) return rc;
-    if (mu || var) HIP_TRY(launch_scatter_posterior(s->P, s->lo, s->n_valid, visited, mu, var, s->stream));
-    if (!var_mean) return BO_OK;
-    bool retried;
-    rc = settle_fit(s, &retried);
-    if (rc != BO_OK) return rc;
-    if (!retried) break;
-  }
+  rc = enqueue_posterior(s, visited, a);
+  if (rc != BO_OK) return rc;
+  if (mu || var) HIP_TRY(launch_scatter_posterior(s->P, s->lo, s->n_valid, visited, mu, var, s->stream));
+  if (!var_mean) return BO_OK;
+  rc = sync_state(s);
+  if (rc != BO_OK) return rc;
   const DevState& h = *s->hstate;
   if (h.status != BO_OK) return fail((bo_status)h.status, "fit failed with status %d", h.status);
   *var_mean = h.var_mean;

@@ -19,8 +19,7 @@ struct bo_session {
   int have_cand;
   int have_fit;
   int n;
-  int fit_attempt;
-  int large_fit;        // the current fit runs on the multi-workgroup path (host jitter retries)
+  int large_fit;        // the current fit runs on the multi-workgroup path
   bo_acq_result* hres;  // pinned host copy of the device result
   bo::DevState* hstate;     // pinned host copy of the device state
   int timing;

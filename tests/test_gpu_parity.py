@@ -173,6 +173,37 @@ def test_jitter_escalation_and_not_pd(bo, n):
     assert list(r.idx) == [-1, -1, -1]
 
 
+@pytest.mark.parametrize("n", [300, 1000])
+def test_async_jitter_escalation_on_device(bo, n):
+    # Section III-B fit with a singular K_nn (a duplicated observation, zero
+    # noise) stepped only through bo_acquire_async: the jitter schedule is
+    # escalated on the device, so the result carries the oracle's accepted
+    # jitter and equals the synchronous step's
+    import torch
+    s = W.make_session(6, (12, 12, 12), n, invalid_frac=0.0)
+    obs = s.obs_idx.copy()
+    obs[-1] = obs[0]
+    y = s.y.copy()
+    X = oracle.normalize_grid(s.levels)
+    f = oracle.fit(X[obs], y, oracle.GP(noise=0.0))
+    assert f.jitter > 0.0
+    S = _session(bo, s, "fp64", n_max=n, gp=bo.GpParams(noise=0.0))
+    acq = bo.AcqParams(mode=0)
+    vis = torch.as_tensor(s.visited()).cuda()
+    out = torch.zeros(bo.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    S.fit(obs, y)
+    S.acquire_async(out, vis, acq)
+    torch.cuda.synchronize()
+    ra = bo.result_from_bytes(out.cpu().numpy().tobytes())
+    assert ra.status == 0 and ra.jitter == f.jitter
+    S.fit(obs, y)
+    r = S.acquire(vis, acq)
+    np.testing.assert_array_equal(ra.idx, r.idx)
+    np.testing.assert_array_equal(ra.score, r.score)
+    assert ra.jitter == r.jitter and ra.var_mean == r.var_mean
+    S.close()
+
+
 def test_error_codes(bo):
     s = W.config_c1(0)
     S = _session(bo, s, "fp64")
