@@ -53,38 +53,58 @@ __device__ __forceinline__ float matern32_r2(int nu2, float r2, float inv_l) {
 constexpr double kAugScale = 1024.0;
 constexpr double kAugPair = 4096.0;
 
+__device__ __forceinline__ uint32_t f16_bits(double v, double* used) {
+  // any high part does (the remainder takes the difference); through FP32,
+  // which has a hardware conversion
+  const _Float16 h = (_Float16)(float)v;
+  *used = (double)h;
+  return __builtin_bit_cast(uint16_t, h);
+}
+
 __device__ __forceinline__ void aug16_row(const double* x, int d, bool obs, uint16_t* row, int w16) {
   double nrm = 0.0;
   for (int j = 0; j < d; ++j) nrm += x[j] * x[j];
   nrm *= kAugScale * kAugScale / kAugPair;
-  const _Float16 n1 = (_Float16)nrm;
-  const _Float16 n2 = (_Float16)(nrm - (double)n1);
-  const _Float16 n3 = (_Float16)(nrm - (double)n1 - (double)n2);
-  _Float16* hi = reinterpret_cast<_Float16*>(row);
-  _Float16* lo = hi + w16;
-  for (int j = 0; j < w16; ++j) {
-    hi[j] = (_Float16)0.0f;
-    lo[j] = (_Float16)0.0f;
-  }
-  for (int j = 0; j < d; ++j) {
-    const double v = (obs ? -2.0 : 1.0) * kAugScale * x[j];
-    const _Float16 h = (_Float16)v;
-    hi[j] = h;
-    lo[j] = (_Float16)(v - (double)h);
-  }
-  const _Float16 pair = (_Float16)kAugPair;
-  if (obs) {
-    hi[d] = n1;
-    lo[d] = n2;
-    hi[d + 1] = pair;
-    hi[d + 2] = n3;
-    hi[d + 3] = pair;
-  } else {
-    hi[d] = pair;
-    hi[d + 1] = n1;
-    lo[d + 1] = n2;
-    hi[d + 2] = pair;
-    hi[d + 3] = n3;
+  uint4* out = reinterpret_cast<uint4*>(row);
+  // entries in groups of eight (one 16-byte store per part and group)
+  for (int g = 0; g < w16; g += 8) {
+    uint32_t hw[4], lw[4];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = g + q;
+      double hi = 0.0, lo = 0.0, hv, lv;
+      if (j < d) {
+        hi = (obs ? -2.0 : 1.0) * kAugScale * x[j];
+        lo = 1.0;  // marks "remainder of hi"
+      } else if (j == d) {
+        if (obs) { hi = nrm; lo = 1.0; } else hi = kAugPair;
+      } else if (j == d + 1) {
+        if (obs) hi = kAugPair; else { hi = nrm; lo = 1.0; }
+      } else if (j == d + 2) {
+        hi = obs ? 2.0 : kAugPair;  // obs: third part of the norm, below
+      } else if (j == d + 3) {
+        hi = obs ? kAugPair : 2.0;  // cand: third part of the norm, below
+      }
+      uint32_t hb, lb = 0;
+      if ((obs && j == d + 2) || (!obs && j == d + 3)) {
+        double n1, n2, n3;
+        (void)f16_bits(nrm, &n1);
+        (void)f16_bits(nrm - n1, &n2);
+        hb = f16_bits(nrm - n1 - n2, &n3);
+      } else {
+        hb = f16_bits(hi, &hv);
+        if (lo != 0.0) lb = f16_bits(hi - hv, &lv);
+      }
+      if (q & 1) {
+        hw[q >> 1] |= hb << 16;
+        lw[q >> 1] |= lb << 16;
+      } else {
+        hw[q >> 1] = hb;
+        lw[q >> 1] = lb;
+      }
+    }
+    out[g / 8] = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+    out[(w16 + g) / 8] = make_uint4(lw[0], lw[1], lw[2], lw[3]);
   }
 }
 
