@@ -232,75 +232,143 @@ def bench_batched(args, torch, bo, W) -> int:
     return 0
 
 
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+class _ServedPool:
+    """The serving form's live sessions on one server: each has at most one
+    request in flight (BO is sequential), evaluates the EI choice of its last
+    result next (closed loop), and retires at 220 observations, when a fresh
+    seeded session takes its place."""
+
+    RETIRE = 220
+
+    def __init__(self, srv, bo, W, prec, rng, seed=0, sessions=1024):
+        self.srv, self.bo, self.W, self.prec, self.rng, self.seed = srv, bo, W, prec, rng, seed
+        self.fresh = 0
+        self.slots = []
+        for s in W.config_c5_population(seed, sessions):
+            self.slots.append(self._open(s))
+        self.idle = list(range(len(self.slots)))
+        self.live = {}
+        self.retired = 0
+
+    def _open(self, s):
+        sid = self.srv.open(s.levels, s.obs_idx, s.y, N=s.N, cand=s.cand, invalid=s.invalid, n_max=256,
+                            precision=self.prec)
+        vis = s.visited().astype(bool)
+        pool = np.flatnonzero((s.invalid == 0) & ~vis)
+        acq = self.bo.AcqParams(mode=1, mu_s=float(np.mean(s.y[:s.n_init])), var_s_mean=0.0)
+        return {"s": s, "sid": sid, "vis": vis, "n": s.n, "next": int(self.rng.choice(pool)), "acq": acq}
+
+    def submit(self, i, t_arrive):
+        c = self.slots[i]
+        idx = c["next"]
+        y = float(c["s"].observe(self.rng, np.array([idx]))[0])
+        c["vis"][idx] = True
+        c["n"] += 1
+        self.live[self.srv.submit(c["sid"], idx, y, True, c["acq"])] = (i, t_arrive)
+
+    def collect(self):
+        """Finished requests: [(latency from submission ms, latency from arrival ms, n_unmasked)]."""
+        out = []
+        now = time.perf_counter()
+        for t in [t for t in list(self.live) if self.srv.poll(t)]:
+            i, t_arrive = self.live.pop(t)
+            r, ms = self.srv.wait(t)
+            assert r.status == 0, r.status
+            c = self.slots[i]
+            c["next"] = int(r.idx[0])
+            out.append((ms, (now - t_arrive) * 1e3, r.n_unmasked))
+            if c["n"] >= self.RETIRE:
+                self.srv.close_session(c["sid"])
+                self.slots[i] = self._open(self.W.c5_fresh_session(self.seed, self.fresh))
+                self.fresh += 1
+                self.retired += 1
+            self.idle.append(i)
+        return out
+
+
+def _served_run(pool, rate, warm, count, rng, limit_s=120.0):
+    """Runs until `warm` + `count` requests have finished (or `limit_s`
+    seconds); rate None: closed loop (every idle session submits at once: the
+    saturated rate), else Poisson arrivals at `rate` requests/s, each to a
+    uniformly random idle session (an arrival with no idle session waits for
+    one).  Statistics over the finished requests after the first `warm`."""
+    done, lat, e2e, unm = 0, [], [], 0
+    t_meas = None
+    total = warm + count
+    t0 = time.perf_counter()
+    t_next = t0
+    pending = []  # arrival times waiting for an idle session
+    while done < total and time.perf_counter() - t0 < limit_s:
+        now = time.perf_counter()
+        if rate is None:
+            while pool.idle:
+                i = pool.idle.pop(int(rng.integers(0, len(pool.idle))))
+                pool.submit(i, now)
+        else:
+            while now >= t_next:
+                pending.append(t_next)
+                t_next += float(rng.exponential(1.0 / rate))
+            while pending and pool.idle:
+                i = pool.idle.pop(int(rng.integers(0, len(pool.idle))))
+                pool.submit(i, pending.pop(0))
+        for ms, ms_e2e, u in pool.collect():
+            done += 1
+            if done == warm:
+                t_meas = time.perf_counter()
+            elif done > warm:
+                lat.append(ms)
+                e2e.append(ms_e2e)
+                unm += u
+    t_run = time.perf_counter() - (t_meas or t0)
+    q = lambda v, p: float(np.percentile(v, p)) if v else None
+    return {"requests": len(lat), "requests_per_s": len(lat) / t_run, "value": unm / t_run,
+            "complete": done >= total,
+            "latency_ms": {"p50": q(lat, 50), "p99": q(lat, 99), "mean": float(np.mean(lat)) if lat else None},
+            "arrival_to_result_ms": {"p50": q(e2e, 50), "p99": q(e2e, 99)}}
+
+
 def bench_serving(args, torch, bo, W) -> int:
-    pop = W.config_c5_population(0)
+    """Serving form: 1,024 live sessions; the saturated request rate from a
+    closed-loop run, then Poisson arrivals at 0.5, 0.8, 0.95 and 1.1 times it
+    (1,000 warm-up and --requests measured requests each) with a 64 GB
+    admission budget, and one run at 0.8 times it with a 512 MB budget that
+    forces admission; the plain per-session path (one step at a time, one
+    stream, same precision) beside it."""
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     prec = args.precision or "fp32"
+    rng = np.random.Generator(np.random.PCG64(17))
+    warm, count = 1000, int(args.requests)
     srv = bo.Server(hbm_budget=64 << 30, max_batch=256, streams=3)
     t0 = time.perf_counter()
-    sids = [srv.open(s.levels, s.obs_idx, s.y, N=s.N, cand=s.cand, invalid=s.invalid, n_max=256, precision=prec)
-            for s in pop]
+    pool = _ServedPool(srv, bo, W, prec, rng)
     t_open = time.perf_counter() - t0
-    rng = np.random.Generator(np.random.PCG64(17))
-    acqs = [bo.AcqParams(mode=1, mu_s=float(np.mean(s.y[:s.n_init])), var_s_mean=0.0) for s in pop]
-    visited = [s.visited().astype(bool) for s in pop]
-    n_obs = [s.n for s in pop]
-    nxt = []
-    for s, v in zip(pop, visited):
-        pool = np.flatnonzero((s.invalid == 0) & ~v)
-        nxt.append(int(rng.choice(pool)))
-
-    def request(i):
-        s = pop[i]
-        idx = nxt[i]
-        y = float(s.observe(rng, np.array([idx]))[0])
-        visited[i][idx] = True
-        n_obs[i] += 1
-        return srv.submit(sids[i], idx, y, True, acqs[i])
-
-    def settle(i, r):
-        assert r.status == 0, r.status
-        nxt[i] = int(r.idx[0])  # closed loop: evaluate the EI choice next
-
-    # capacity: every session submits at once
-    t0 = time.perf_counter()
-    burst = [(i, request(i)) for i in range(len(pop))]
-    unm = 0
-    for i, t in burst:
-        r, _ = srv.wait(t)
-        settle(i, r)
-        unm += r.n_unmasked
-    t_burst = time.perf_counter() - t0
-    cap_rps = len(pop) / t_burst
-    # Poisson arrivals at 60% of that capacity, sessions chosen among the idle ones
-    rate = 0.6 * cap_rps
-    M = int(args.requests)
-    live = {}
-    idle = list(range(len(pop)))
-    lat, unmasked = [], 0
-    t_start = time.perf_counter()
-    t_next = t_start
-    sent = 0
-    while sent < M or live:
-        now = time.perf_counter()
-        if sent < M and now >= t_next and idle:
-            i = idle.pop(int(rng.integers(0, len(idle))))
-            live[request(i)] = i
-            sent += 1
-            t_next += float(rng.exponential(1.0 / rate))
-            continue
-        for t in [t for t in list(live) if srv.poll(t)]:
-            i = live.pop(t)
-            r, ms = srv.wait(t)
-            settle(i, r)
-            lat.append(ms)
-            unmasked += r.n_unmasked
-            if n_obs[i] < 256:  # a session retires when its fit is full
-                idle.append(i)
-    t_run = time.perf_counter() - t_start
+    sat = _served_run(pool, None, warm, count, rng)
+    lam = sat["requests_per_s"]
+    _progress(f"saturated: {lam:.0f} requests/s, p50 {sat['latency_ms']['p50']} ms")
+    sweep = {}
+    for f in (0.5, 0.8, 0.95, 1.1):
+        sweep[str(f)] = dict(_served_run(pool, f * lam, warm, count, rng), rate_rps=f * lam)
+        _progress(f"{f} x saturated: {sweep[str(f)]['requests']} requests, p99 {sweep[str(f)]['latency_ms']['p99']} ms")
     st = srv.stats()
+    retired = pool.retired
+    srv.close()
+    # forced admission: the same sessions under a 512 MB budget
+    srv2 = bo.Server(hbm_budget=512 << 20, max_batch=256, streams=3)
+    pool2 = _ServedPool(srv2, bo, W, prec, np.random.Generator(np.random.PCG64(18)))
+    st2_open = srv2.stats()
+    forced = dict(_served_run(pool2, 0.8 * lam, warm, count, rng), rate_rps=0.8 * lam,
+                  sessions_resident_at_open=st2_open["sessions_resident"],
+                  sessions_waiting_at_open=st2_open["sessions_waiting"])
+    srv2.close()
+    _progress(f"forced admission: {forced['requests']} requests, complete {forced['complete']}")
     # the plain per-session path on the first 64 sessions, one request at a time
+    pop = W.config_c5_population(0)
+    acqs = [bo.AcqParams(mode=1, mu_s=float(np.mean(s.y[:s.n_init])), var_s_mean=0.0) for s in pop[:64]]
     P = []
     for s in pop[:64]:
         x = bo.Session(s.N, s.d, 256, prec, device=dev)
@@ -315,8 +383,8 @@ def bench_serving(args, torch, bo, W) -> int:
         i = k % 64
         x, o, yv, v = P[i]
         s = pop[i]
-        pool = np.flatnonzero((s.invalid == 0) & (v == 0))
-        idx = int(pool[k % pool.size])
+        cand_pool = np.flatnonzero((s.invalid == 0) & (v == 0))
+        idx = int(cand_pool[k % cand_pool.size])
         ts = time.perf_counter()
         o.append(idx)
         yv.append(float(s.observe(rng, np.array([idx]))[0]))
@@ -326,18 +394,22 @@ def bench_serving(args, torch, bo, W) -> int:
         plat.append((time.perf_counter() - ts) * 1e3)
         punm += r.n_unmasked
     t_plain = time.perf_counter() - t0
+    for x in P:
+        x[0].close()
+    head = sweep["0.8"]
     line = {
         "metric": "candidate posterior+acquisition evals/s; BO step p50/p99 latency",
-        "value": unmasked / t_run, "unit": "candidate-evals/s",
-        "n_gpus": 1, "steps": len(lat), "warmup": len(pop), "ms_per_step": t_run / max(1, len(lat)) * 1e3,
+        "value": head["value"], "unit": "candidate-evals/s",
+        "n_gpus": 1, "steps": head["requests"], "warmup": warm,
+        "ms_per_step": 1e3 / head["requests_per_s"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
-        "config": {"workload": "c5: " + MULTI["c5"] + f", {prec.upper()} posterior", "sessions": len(pop),
-                   "arrival_rate_rps": rate,
-                   "open_s": t_open},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "mean": float(np.mean(lat))},
-        "requests_per_s": len(lat) / t_run,
-        "burst_capacity_rps": cap_rps,
+        "config": {"workload": "c5: " + MULTI["c5"] + f", {prec.upper()} posterior", "sessions": len(pool.slots),
+                   "headline_rate": "0.8 x saturated", "open_s": t_open},
+        "latency_ms": head["latency_ms"],
+        "saturated": sat,
+        "sweep": sweep,
+        "forced_admission_512MB": forced,
+        "sessions_retired_and_replaced": retired,
         "server": st,
         "plain_path": {"requests": len(plat), "value": punm / t_plain, "requests_per_s": len(plat) / t_plain,
                        "latency_ms": {"p50": float(np.percentile(plat, 50)), "p99": float(np.percentile(plat, 99))}},
@@ -345,9 +417,6 @@ def bench_serving(args, torch, bo, W) -> int:
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
-    for x in P:
-        x[0].close()
-    srv.close()
     return 0
 
 
@@ -436,7 +505,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + sorted(MULTI))
-    ap.add_argument("--requests", type=int, default=6000, help="c5: requests in the Poisson run")
+    ap.add_argument("--requests", type=int, default=10000,
+                    help="c5: measured requests per arrival rate (after 1,000 warm-up requests)")
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default=None,
                     help="c1-c3: posterior arithmetic other than the workload's own")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

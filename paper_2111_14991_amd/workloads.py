@@ -272,6 +272,14 @@ def config_c5_population(seed: int = 0, sessions: int = 1024) -> List[Session]:
     return [_population_member(rng, seed, 10, 200) for _ in range(sessions)]
 
 
+def c5_fresh_session(seed: int, k: int) -> Session:
+    """The k-th replacement session of the serving form (drawn as the
+    population's members, from its own seeded generator): a live session
+    retires at 220 observations and a fresh one takes its place."""
+    rng = np.random.Generator(np.random.PCG64([seed + 7919, k + 1]))
+    return _population_member(rng, seed, 10, 200)
+
+
 def tiny_session(seed: int, levels: Sequence[int] = (4, 3, 5), n_obs: int = 5,
                  invalid_frac: float = 0.2) -> Session:
     """A few-dozen-point space for brute-force checks."""
