@@ -55,12 +55,18 @@ typedef enum {
 
 /* Arithmetic of the posterior (the fit is FP64 in every mode).
  *  BO_FP64   : cross-covariance, variance contraction and mean in FP64.
- *  BO_FP32   : cross-covariance and mean in FP64; variance contraction on FP32
- *              matrix cores over chunks of 16 observations, chunks summed in FP64.
- *  BO_BF16X3 : cross-covariance in FP32, split into bfloat16 high and low parts;
- *              variance contraction as three bfloat16 matrix-core products
- *              (hi*hi + hi*lo + lo*hi) with FP32 accumulation; mean in FP64
- *              from the FP32 covariances. */
+ *  BO_FP32   : mean and variance stored in FP32.  For n <= 256 they come from
+ *              the same FP64 products as BO_FP64 (an FP32 contraction cannot
+ *              hold a variance that is small next to the prior to 1e-6 of
+ *              itself); above, the variance contraction runs on FP32 matrix
+ *              cores over the covariance residuals after the nearest
+ *              observation, chunks of 16 observations summed in FP64, with
+ *              FP64 rows where the residual part dominates.
+ *  BO_BF16X3 : squared distances from three FP16 matrix-core products of
+ *              augmented coordinates, cross-covariance in FP32, split into
+ *              bfloat16 high and low parts; variance contraction as three
+ *              bfloat16 matrix-core products (hi*hi + hi*lo + lo*hi) with FP32
+ *              accumulation; mean in FP64 from the FP32 covariances. */
 typedef enum { BO_FP64 = 0, BO_FP32 = 1, BO_BF16X3 = 2 } bo_precision;
 
 /* Acquisition-function bits (Section III-C). */
@@ -277,21 +283,24 @@ bo_status bo_get_timing(bo_session* s, float* fit_ms, float* posterior_ms, float
 /* ------------------------------------------------------------------------
  * Batched form: many independent sessions advance one step together.
  *
- * One persistent kernel runs every session's FP64 fit (n <= 256), posterior
- * tiles and acquisition chunks from a single work queue; the launch is
- * captured once in a HIP graph (plan upload, kernel, result download) and
- * replayed each step.  Per-session results equal those of bo_gp_fit +
- * bo_acquire on the same session up to the summation order of the mean
- * variance.  Sessions must be FP64 or FP32, have candidates set, and have no
+ * One HIP graph, captured once and replayed each step, runs every session's
+ * FP64 fit (n <= 256), the posterior over every session's candidates (one
+ * launch per precision, in 64-candidate slots), the exploration factors, the
+ * acquisition chunks and the selections, between a plan upload and a result
+ * download; each kernel's grid is set to the step's work before the replay.
+ * Per-session results equal those of bo_gp_fit + bo_acquire on the same
+ * session bit for bit (the same kernels per candidate and the same reduction
+ * orders).  Sessions must be FP64 or FP32, have candidates set, and have no
  * work pending on their own streams; the batch runs on its own stream.
  * ---------------------------------------------------------------------- */
 typedef struct bo_batch bo_batch;
 
-/* Tile shapes and scheduling of the batched kernel. */
+/* Work sizes and scheduling of the batched step. */
 typedef struct {
-  int32_t tile_rows;  /* candidates per wave in a posterior tile: 16 or 32 (32 applies where
-                         the kernel's LDS holds it, n_pad <= 128 for FP32) */
-  int32_t acq_chunk;  /* candidates per acquisition work item, a positive multiple of 2048 */
+  int32_t post_order; /* posterior slots: 0, the sessions of the largest fits first; 1, in
+                           the fit order */
+  int32_t acq_chunk;  /* candidates per acquisition workgroup, a positive multiple of 2048
+                         (raised where a session would need more than 512 chunks) */
   int32_t fit_order;  /* 0: sessions in order; 1: largest fit first */
   int32_t reserved;
 } bo_batch_config;
@@ -302,7 +311,7 @@ bo_status bo_batch_workspace_query(int32_t count, size_t* bytes);
 /* Bind `count` distinct sessions (host array of handles, kept by reference:
  * they must outlive the batch) over a caller-owned, 256-byte-aligned device
  * workspace.  stream: hipStream_t as void*; NULL creates a private blocking
- * stream.  Default config {16, 8192, 1}. */
+ * stream.  Default config {0, 8192, 1}. */
 bo_status bo_batch_create(bo_batch** out, bo_session* const* sessions, int32_t count, void* workspace,
                           size_t bytes, void* stream);
 void bo_batch_destroy(bo_batch* b);
@@ -326,8 +335,8 @@ bo_status bo_batch_step(bo_batch* b, const int64_t* const* obs_idx, const double
                         const uint8_t* const* visited, const bo_acq_params* params, bo_acq_result* out,
                         float* graph_ms);
 
-/* Autotuner: runs the step `reps` + 1 times for each tile shape / chunk /
- * fit order of a fixed candidate set, keeps the configuration with the
+/* Autotuner: runs the step `reps` + 1 times for each slots-per-workgroup /
+ * chunk / fit order of a fixed candidate set, keeps the configuration with the
  * lowest median graph time, stores it in the batch and returns it in
  * *chosen (nullable).  out receives the results of the last run. */
 bo_status bo_batch_tune(bo_batch* b, const int64_t* const* obs_idx, const double* const* y, const int32_t* n,
@@ -341,8 +350,8 @@ bo_status bo_batch_tune(bo_batch* b, const int64_t* const* obs_idx, const double
  * extension of the device-resident factor; for an evaluation that failed,
  * valid = 0, only the visited mark) and returns the step's result.  A
  * scheduler thread gathers pending requests of idle sessions (one request in
- * flight per session, oldest first) into launches of the batched persistent
- * kernel on up to `streams` launch contexts, each with its own stream, so
+ * flight per session, oldest first) into replays of the batched step graph
+ * on up to `streams` launch contexts, each with its own stream, so
  * that requests arriving while launches run are admitted as soon as a context
  * frees up and launches overlap on the device.  A session's device state is
  * allocated when it fits in the memory budget; until then it waits, with its
@@ -354,7 +363,7 @@ typedef struct {
   size_t hbm_budget;       /* device bytes for session state (bo_server_session_bytes each) */
   int32_t max_batch;       /* most requests in one launch, 1..4096 */
   int32_t streams;         /* launches in flight at once, 1..8 */
-  bo_batch_config tiles;   /* tile shapes of the batched kernel */
+  bo_batch_config tiles;   /* work sizes of the batched step */
 } bo_server_config;
 
 typedef struct {

@@ -58,7 +58,7 @@ class bo_fit_info(C.Structure):
 
 
 class bo_batch_config(C.Structure):
-    _fields_ = [("tile_rows", C.c_int32), ("acq_chunk", C.c_int32), ("fit_order", C.c_int32),
+    _fields_ = [("post_order", C.c_int32), ("acq_chunk", C.c_int32), ("fit_order", C.c_int32),
                 ("reserved", C.c_int32)]
 
 
@@ -474,14 +474,14 @@ class Batch:
         pa = (bo_acq_params * k)(*[a.c() for a in acqs])
         return po, py, pn, pv, pa
 
-    def set_config(self, tile_rows=16, acq_chunk=8192, fit_order=1):
-        c = bo_batch_config(tile_rows, acq_chunk, fit_order, 0)
+    def set_config(self, post_order=0, acq_chunk=8192, fit_order=1):
+        c = bo_batch_config(post_order, acq_chunk, fit_order, 0)
         _check(lib().bo_batch_set_config(self.h, C.byref(c)), "bo_batch_set_config")
 
     def config(self):
         c = bo_batch_config()
         _check(lib().bo_batch_get_config(self.h, C.byref(c)), "bo_batch_get_config")
-        return {"tile_rows": c.tile_rows, "acq_chunk": c.acq_chunk, "fit_order": c.fit_order}
+        return {"post_order": c.post_order, "acq_chunk": c.acq_chunk, "fit_order": c.fit_order}
 
     def set_timing(self, enable: bool = True):
         _check(lib().bo_batch_set_timing(self.h, 1 if enable else 0), "bo_batch_set_timing")
@@ -500,7 +500,7 @@ class Batch:
         out = (bo_acq_result * self.count)()
         c = bo_batch_config()
         _check(lib().bo_batch_tune(self.h, po, py, pn, pv, pa, int(reps), C.byref(c), out), "bo_batch_tune")
-        return {"tile_rows": c.tile_rows, "acq_chunk": c.acq_chunk, "fit_order": c.fit_order}
+        return {"post_order": c.post_order, "acq_chunk": c.acq_chunk, "fit_order": c.fit_order}
 
 
 def server_session_bytes(N: int, d: int, n_max: int, precision="fp32") -> int:
@@ -515,10 +515,10 @@ class Server:
     requests are batched continuously by the library's scheduler thread."""
 
     def __init__(self, hbm_budget: int = 64 << 30, max_batch: int = 256, streams: int = 2,
-                 tile_rows: int = 16, acq_chunk: int = 8192, fit_order: int = 1):
+                 post_order: int = 0, acq_chunk: int = 8192, fit_order: int = 1):
         _torch()
         cfg = bo_server_config(int(hbm_budget), int(max_batch), int(streams),
-                               bo_batch_config(tile_rows, acq_chunk, fit_order, 0))
+                               bo_batch_config(post_order, acq_chunk, fit_order, 0))
         h = C.c_void_p()
         _check(lib().bo_server_create(C.byref(h), C.byref(cfg)), "bo_server_create")
         self.h = h

@@ -14,6 +14,10 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     # packed FP32 instructions stay off: the compiler must not form them
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a * b + c is fused within one expression only, never across statements,
+    # so that a device function rounds the same in every kernel it is
+    # inlined into (the batched and single-session paths agree bit for bit)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

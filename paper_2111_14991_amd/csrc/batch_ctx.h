@@ -1,6 +1,6 @@
-// One launch context of the batched step (the persistent kernel in
-// k_batch.hip): device plan, per-session flags and results in a caller-owned
-// workspace, pinned host mirrors, a stream and the captured graph.  Used by
+// One launch context of the batched step (the graph of kernels in
+// k_batch.hip): device plan and results in a caller-owned workspace, pinned
+// host mirrors, a stream and the captured graph.  Used by
 // the bo_batch entry points and by the server, which keeps one context per
 // stream so that launches overlap.
 #pragma once
@@ -29,6 +29,8 @@ struct BatchItem {
   uint8_t* mark;           // device, nullable: mark[new_idx] = 1 before the fit
 };
 
+constexpr int kBatchNodes = 6;  // fits, posterior FP64 and FP32, exploration factors, chunks, selections
+
 class BatchCtx {
  public:
   static size_t bytes(int cap);
@@ -49,14 +51,17 @@ class BatchCtx {
   bo_status build_plan(const BatchItem* items, int count, const bo_batch_config& cfg);
   bo_status capture();
   unsigned char* plan_dev = nullptr;
-  unsigned char* sync = nullptr;
   bo_acq_result* res_dev = nullptr;
-  unsigned char* ctl = nullptr;
   unsigned char* plan_host = nullptr;
   unsigned char* res_host = nullptr;
   size_t plan_sz = 0, res_sz = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  hipGraphNode_t knode[kBatchNodes] = {};  // the kernel nodes, in launch order
+  unsigned kgrid[kBatchNodes] = {};        // their grids in the instantiated graph
+  unsigned grids[kBatchNodes] = {};        // the grids the current plan needs
+  unsigned char* karg_plan = nullptr;      // kernel arguments (stable addresses)
+  int karg_cap = 0;
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t done_ev = nullptr;
   std::vector<int> order_scratch;

@@ -15,6 +15,7 @@ constexpr int kMaxN = 1024;
 constexpr int kTile = 32;           // fit tile edge (FP64)
 constexpr int kSmallFitMax = 256;   // most observations of the one-workgroup fit (batched, served, append)
 constexpr int kPlainSmallMax = 128; // a single session's fit above this uses the multi-workgroup fit
+constexpr int kRegMax = 256;        // n_pad of the register-resident posterior (FP64 products, FP64 and FP32)
 constexpr int kAcqThreads = 256;
 constexpr int kAcqPerThread = 2;
 constexpr int kAcqMaxBlocks = 512;

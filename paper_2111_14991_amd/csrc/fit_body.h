@@ -748,6 +748,10 @@ __device__ __forceinline__ double linv_at(const FitArgs& a, int row, int col) {
 
 // FP64 / FP32, 16x16x4 operand: fragment (J, t) at 2J(J+1) + t, t <= 4J+3;
 // lane l holds L^-1[16J + l%16][4t + l/16] (the transpose, as the B operand).
+// FP64 values for the FP64 mode and for every fit of n_pad <= kRegMax (whose
+// posterior takes FP64 products in both modes), FP32 values otherwise.
+__device__ __forceinline__ bool pack_f64(const FitArgs& a) { return a.prec == BO_FP64 || a.n_pad <= kRegMax; }
+
 __device__ void pack_elem16(const FitArgs& a, int64_t e) {
   const int64_t f = e >> 6;
   const int l = (int)(e & 63);
@@ -756,7 +760,7 @@ __device__ void pack_elem16(const FitArgs& a, int64_t e) {
   while (2LL * J * (J + 1) > f) --J;
   const int t = (int)(f - 2LL * J * (J + 1));
   const double v = linv_at(a, 16 * J + (l & 15), 4 * t + (l >> 4));
-  if (a.prec == BO_FP64) ((double*)a.Bpk)[e] = v;
+  if (pack_f64(a)) ((double*)a.Bpk)[e] = v;
   else ((float*)a.Bpk)[e] = (float)v;
 }
 
@@ -820,7 +824,7 @@ constexpr int NTEAM = kSmallThreads / TT;
 // The whole fit of n <= 256 observations by one workgroup of kSmallThreads
 // threads: gather, build, factor and invert with the jitter schedule, alpha
 // and the packed operand.  s_raw: kSmallLdsBytes of LDS.
-__device__ void fit_small_run(const FitArgs& a, unsigned char* s_raw) {
+__device__ __forceinline__ void fit_small_run(const FitArgs& a, unsigned char* s_raw) {
   // tiles[0], tiles[1]: Dinv / factor of the diagonal tile in step A, team 0's
   // operands in step B; tiles[2], tiles[3]: team scratch (A) / team 1 (B)
   Tile* tiles = reinterpret_cast<Tile*>(s_raw);
@@ -925,7 +929,7 @@ __device__ void fit_small_run(const FitArgs& a, unsigned char* s_raw) {
 // (n0 + 1)-point factorization, the whole fit is redone by fit_small_run,
 // jitter schedule included: the result is then the refit's by construction.
 // One workgroup of kSmallThreads threads, n <= 256; s_raw: kSmallLdsBytes.
-__device__ void append_run(const FitArgs& a, unsigned char* s_raw) {
+__device__ __forceinline__ void append_run(const FitArgs& a, unsigned char* s_raw) {
   __shared__ int s_mode;  // 0: append, 1: refit, 2: bad observation
   __shared__ int s_pos0;
   double* s_k = reinterpret_cast<double*>(s_raw);    // [256]

@@ -40,12 +40,13 @@ __global__ __launch_bounds__(256) void k_post16(PostArgs p) {
     p.vslots[blockIdx.x].sum = s;
     p.vslots[blockIdx.x].count = c;
   }
-  if (last_block(&p.st->ticket_post, &s_last)) finish_lambda(p, gridDim.x, s_rsum, s_rcnt);
+  if (last_block(&p.st->ticket_post, &s_last)) finish_lambda(p, gridDim.x, s_rsum, s_rcnt, blockDim.x);
 }
 
 // FP64 posterior with register-resident accumulators, n_pad = 16 JB <= 256,
-// d <= DM: four waves of 16 candidates per workgroup, no LDS operand.
-template <int JB, int DM>
+// d <= DM: four waves of 16 candidates per workgroup, no LDS operand; OUT32:
+// the FP32 mode (FP32 mean and variance from the same FP64 products).
+template <int JB, int DM, bool OUT32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_post16r(PostArgs p) {
   __shared__ double s_wsum[4];
   __shared__ int64_t s_wcnt[4];
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   stage_obs(p, s_xo, s_alpha);
   double part;
   int64_t cnt;
-  post16_wave_reg<JB, DM>(p, row0, s_xo, s_alpha, &part, &cnt);
+  post16_wave_reg<JB, DM, OUT32>(p, row0, s_xo, s_alpha, &part, &cnt);
   if (l == 0) {
     s_wsum[w] = part;
     s_wcnt[w] = cnt;
@@ -76,64 +77,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     p.vslots[blockIdx.x].sum = s;
     p.vslots[blockIdx.x].count = c;
   }
-  if (last_block(&p.st->ticket_post, &s_last)) finish_lambda(p, gridDim.x, s_rsum, s_rcnt);
+  if (last_block(&p.st->ticket_post, &s_last)) finish_lambda(p, gridDim.x, s_rsum, s_rcnt, blockDim.x);
 }
 
-// FP32 (compensated) counterpart of k_post16r.  The residuals kept between
-// the passes and the last workgroup's reduction scratch share one LDS array
-// (the reduction runs after the workgroup's posterior), which keeps the
-// workgroup within 80 KB: two per CU.
-template <int JB, int DM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_post16r32(PostArgs p) {
-  constexpr int kStored = reg32_stored_steps(JB) * 64;  // residual floats per wave
-  constexpr int kRed = 256 * (sizeof(double) + sizeof(int64_t)) / sizeof(float);
-  constexpr int kR = 4 * kStored > kRed ? 4 * kStored : kRed;
-  __shared__ double s_wsum[4];
-  __shared__ int64_t s_wcnt[4];
-  __shared__ __align__(16) float s_r[kR];
-  __shared__ int s_last;
-  __shared__ double s_xo[16 * JB * kObsPitch];
-  __shared__ double s_alpha[16 * JB];
-  if (p.st->status != BO_OK) return;
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * 16;
-  stage_obs(p, s_xo, s_alpha);
-  double part;
-  int64_t cnt;
-  post16_wave_reg32<JB, DM>(p, row0, s_xo, s_alpha, s_r + w * kStored, &part, &cnt);
-  if (l == 0) {
-    s_wsum[w] = part;
-    s_wcnt[w] = cnt;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    int64_t c = 0;
-    for (int i = 0; i < 4; ++i) {
-      s += s_wsum[i];
-      c += s_wcnt[i];
-    }
-    p.vslots[blockIdx.x].sum = s;
-    p.vslots[blockIdx.x].count = c;
-  }
-  if (last_block(&p.st->ticket_post, &s_last))
-    finish_lambda(p, gridDim.x, (double*)s_r, (int64_t*)(s_r + 256 * sizeof(double) / sizeof(float)));
-}
-
-template <int JB>
-static void launch_post16r32(const PostArgs& a, int grid, hipStream_t st) {
-  if (a.d <= 8)
-    hipLaunchKernelGGL((k_post16r32<JB, 8>), dim3(grid), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_post16r32<JB, kMaxD>), dim3(grid), dim3(256), 0, st, a);
-}
-
-template <int JB>
+template <int JB, bool OUT32>
 static void launch_post16r(const PostArgs& a, int grid, hipStream_t st) {
   if (a.d <= 8)
-    hipLaunchKernelGGL((k_post16r<JB, 8>), dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_post16r<JB, 8, OUT32>), dim3(grid), dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL((k_post16r<JB, kMaxD>), dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_post16r<JB, kMaxD, OUT32>), dim3(grid), dim3(256), 0, st, a);
 }
 
 int post16_rows_per_block(int prec, int n_pad) { return 16 * post16_waves(prec, n_pad); }
@@ -149,10 +101,10 @@ hipError_t launch_posterior(const DevPtrs& P, const Layout& Lo, const GpConst& g
     grid = grid > 0 ? grid : 1;
     const bool f64 = Lo.prec == BO_FP64;
     switch (a.n_pad >> 4) {  // n_pad is a multiple of 64
-      case 4: f64 ? launch_post16r<4>(a, grid, st) : launch_post16r32<4>(a, grid, st); break;
-      case 8: f64 ? launch_post16r<8>(a, grid, st) : launch_post16r32<8>(a, grid, st); break;
-      case 12: f64 ? launch_post16r<12>(a, grid, st) : launch_post16r32<12>(a, grid, st); break;
-      case 16: f64 ? launch_post16r<16>(a, grid, st) : launch_post16r32<16>(a, grid, st); break;
+      case 4: f64 ? launch_post16r<4, false>(a, grid, st) : launch_post16r<4, true>(a, grid, st); break;
+      case 8: f64 ? launch_post16r<8, false>(a, grid, st) : launch_post16r<8, true>(a, grid, st); break;
+      case 12: f64 ? launch_post16r<12, false>(a, grid, st) : launch_post16r<12, true>(a, grid, st); break;
+      case 16: f64 ? launch_post16r<16, false>(a, grid, st) : launch_post16r<16, true>(a, grid, st); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

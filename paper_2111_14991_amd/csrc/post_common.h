@@ -2,6 +2,8 @@
 // the FP64 / FP32 modes, and the last-workgroup reduction of the mean variance
 // and the exploration factor.
 #pragma once
+#include <type_traits>
+
 #include "bo_internal.h"
 #include "bo_device.h"
 
@@ -32,18 +34,22 @@ struct PostArgs {
 
 // Last workgroup of a posterior launch: fixed-order reduction of the slots,
 // mean variance and exploration factor (Section III-F).  Every thread of the
-// workgroup calls it; s_sum / s_cnt hold blockDim.x entries.
-__device__ inline void finish_lambda(const PostArgs& p, int nslots, double* s_sum, int64_t* s_cnt) {
-  const int t = threadIdx.x, nt = blockDim.x;
+// workgroup calls it; the first nt (a power of two, at most blockDim.x) do
+// the reduction, whose order depends on nt alone, so that a workgroup of any
+// size reproduces another's sum bit for bit; s_sum / s_cnt hold nt entries.
+__device__ inline void finish_lambda(const PostArgs& p, int nslots, double* s_sum, int64_t* s_cnt, int nt) {
+  const int t = threadIdx.x;
   const int per = (nslots + nt - 1) / nt;
-  double sum = 0.0;
-  int64_t cnt = 0;
-  for (int s = t * per; s < (t + 1) * per && s < nslots; ++s) {
-    sum += p.vslots[s].sum;
-    cnt += p.vslots[s].count;
+  if (t < nt) {
+    double sum = 0.0;
+    int64_t cnt = 0;
+    for (int s = t * per; s < (t + 1) * per && s < nslots; ++s) {
+      sum += p.vslots[s].sum;
+      cnt += p.vslots[s].count;
+    }
+    s_sum[t] = sum;
+    s_cnt[t] = cnt;
   }
-  s_sum[t] = sum;
-  s_cnt[t] = cnt;
   __syncthreads();
   for (int off = nt / 2; off > 0; off >>= 1) {
     if (t < off) {
@@ -422,7 +428,7 @@ __device__ void post16_wave(const PostArgs& p, int64_t row0, double* kt, double*
   *cnt_out = cnt;
 }
 
-constexpr int kRegJB = 16;     // n_pad <= 256 takes the register-resident FP64 posterior
+constexpr int kRegJB = kRegMax / 16;  // n_pad <= kRegMax takes the register-resident posterior
 constexpr int kObsPitch = kMaxD + 1;  // LDS row pitch of the staged observations
 
 // Stages the observation coordinates (n_pad rows, pitch kObsPitch, zero past
@@ -450,8 +456,11 @@ __device__ inline void stage_obs(const PostArgs& p, double* xs, double* as) {
 // as stage_obs leaves them; the candidate's first DM coordinates (DM >= d)
 // from HBM.  The shape is a template parameter, so every step is
 // straight-line code: the B loads of its live blocks, the kernel value, their
-// MFMAs.  Same outputs and slot partial as post16_wave<false>.
-template <int JB, int DM>
+// MFMAs.  Same outputs and slot partial as post16_wave<false>.  OUT32: the
+// FP32 mode, whose mean and variance are stored in FP32 (its products stay
+// FP64: an FP32 contraction cannot hold the variance to 1e-6 of itself where
+// it is small next to the prior, which is most of a well-sampled space).
+template <int JB, int DM, bool OUT32 = false>
 __device__ void post16_wave_reg(const PostArgs& p, int64_t row0, const double* xs, const double* as,
                                 double* part_out, int64_t* cnt_out) {
   static_assert(JB >= 1 && JB <= kRegJB && DM <= kMaxD, "shape");
@@ -470,8 +479,9 @@ __device__ void post16_wave_reg(const PostArgs& p, int64_t row0, const double* x
   const auto X64 = gptr(uni(p.X64));
   const auto orig = gptr(uni(p.orig));
   const auto visited = gptr(uni(p.visited));
-  const auto mu = gptr((double*)uni(p.mu));
-  const auto var = gptr((double*)uni(p.var));
+  using out_t = typename std::conditional<OUT32, float, double>::type;
+  const auto mu = gptr((out_t*)uni(p.mu));
+  const auto var = gptr((out_t*)uni(p.var));
   const double mean_y = uni(p.st)->mean_y;
   const int64_t my_row = row0 + (l & 15);
   double xr[DM];
@@ -536,7 +546,7 @@ __device__ void post16_wave_reg(const PostArgs& p, int64_t row0, const double* x
   }
   double part = 0.0;
   int64_t cnt = 0;
-  if (l < 16 && my_row < n_valid) mu[my_row] = mean_y + mp;
+  if (l < 16 && my_row < n_valid) mu[my_row] = (out_t)(mean_y + mp);
   if ((l & 15) == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -544,7 +554,7 @@ __device__ void post16_wave_reg(const PostArgs& p, int64_t row0, const double* x
       if (r < n_valid) {
         double v = amp - sq[i];
         v = v > 0.0 ? v : 0.0;
-        var[r] = v;
+        var[r] = (out_t)v;
         if (!(visited && visited[orig[r]])) {
           part += v;
           ++cnt;
@@ -559,313 +569,6 @@ __device__ void post16_wave_reg(const PostArgs& p, int64_t row0, const double* x
   *part_out = part;
   *cnt_out = cnt;
 }
-
-// FP32 mode of post16_wave_reg (the compensated scheme of post16_wave<true>):
-// the wave first finds each row's nearest observation p (four lanes scan
-// disjoint observations, then compare distance and index), then in k-outer
-// order generates the FP64 k* of its A element, adds k*_i alpha_i to the FP64
-// mean and feeds the residual r_i = k*_i - (k*_p / K_pp) K_pi (zero at i = p),
-// rounded to FP32, to the FP32 16x16x4 products of every live column block.
-// A block's FP32 sums cover 4 k-steps (16 observations) and are then added
-// into its FP64 sums.  var = amp - k*_p^2 / K_pp - |L^-1 r|^2; where the
-// FP32 part is more than a quarter of what remains, the block of 16 rows is
-// redone with FP64 products against L^-1 itself (fallback).  With more than
-// 8 column blocks the FP32 and FP64 sums of all of them do not fit in
-// registers: the blocks run in two or three passes; each pass generates the
-// k-steps from its first block's diagonal on and leaves their FP32 residuals
-// in rbuf (reg32_stored_steps(JB) x 64 floats per wave), the later passes
-// read the earlier k-steps back instead of generating them again.  Same
-// outputs and slot partial as post16_wave<true>.
-template <int JB, int DM>
-struct Reg32 {
-  static constexpr int JH = JB > 8 ? JB / 2 : JB;  // split of the FP64 fallback
-  const PostArgs& p;
-  const double* xs;
-  const double* as;
-  float* rbuf;
-  int l, my_k, n, ld, bi;
-  double amp, c1, c2, c, mp;
-  double xr[DM];
-  gptr_t<const double> krow;
-  __amdgpu_buffer_rsrc_t rB;
-  double sq[4];
-
-  __device__ double dist2(int i) const { return dist2_pairs<DM>(xr, xs + i * kObsPitch); }
-  __device__ double kfun(double s) const {
-    const double rho = c1 * sqrt(s);
-    return amp * (fma(rho, fma(c2, rho, 1.0), 1.0) * exp(-rho));  // as KStar
-  }
-  // residual of k-step t, FP64; the mean takes k*_i alpha_i when `mean`
-  __device__ double resid(int t, bool mean) {
-    const int i = 4 * t + my_k;
-    const double kr = krow[i];
-    const double kv = i < n ? kfun(dist2(i)) : 0.0;
-    if (mean) mp = fma(kv, as[i], mp);
-    return (i < n && i != bi) ? kv - c * kr : 0.0;
-  }
-  __device__ float bval(int J, int t) const {
-    return __builtin_bit_cast(float,
-                              __builtin_amdgcn_raw_buffer_load_b32(rB, l * 4, (2 * J * (J + 1) + t) * 64 * 4, 0));
-  }
-  // blocks JA .. JZ-1 over k-steps 0 .. 4 JZ - 1; the k-steps below TS = 4 JA
-  // come from rbuf, the others are generated (and stored in rbuf when STORE)
-  template <int JA, int JZ, int TS, bool STORE>
-  __device__ void pass() {
-    static_assert(TS == 4 * JA, "the k-steps before JA come from the first pass");
-    constexpr int NQ = JZ - JA;
-    f32x4 acc[NQ];
-    f64x4 a64[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      acc[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
-      a64[q] = (f64x4){0.0, 0.0, 0.0, 0.0};
-    }
-    auto flush = [&](int q0) {
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        if (q >= q0) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) a64[q][i] += (double)acc[q][i];
-          acc[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
-        }
-      }
-    };
-    // k-steps before block JA's diagonal: every block of the range is live
-#pragma unroll 1
-    for (int g = 0; g < JA; ++g) {
-#pragma unroll 1
-      for (int tt = 0; tt < 4; ++tt) {
-        const int t = 4 * g + tt;
-        float bq[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) bq[q] = bval(JA + q, t);
-        const float rf = rbuf[t * 64 + l];  // stored by the first pass (TS = 4 JA)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rf, bq[q], acc[q], 0, 0, 0);
-      }
-      flush(0);
-    }
-    // then phase J0 = JA + q0: blocks q0 .. NQ-1
-#pragma unroll
-    for (int q0 = 0; q0 < NQ; ++q0) {
-#pragma unroll 1
-      for (int tt = 0; tt < 4; ++tt) {
-        const int t = 4 * (JA + q0) + tt;
-        float bq[NQ];
-#pragma unroll
-        for (int q = q0; q < NQ; ++q) bq[q] = bval(JA + q, t);
-        // k-steps from JA on are generated here (TS <= 4 JA)
-        const float rf = (float)resid(t, true);
-        if (STORE) rbuf[t * 64 + l] = rf;
-#pragma unroll
-        for (int q = q0; q < NQ; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(rf, bq[q], acc[q], 0, 0, 0);
-      }
-      flush(q0);
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) sq[i] += a64[q][i] * a64[q][i];
-    // the squares are summed here, not after the later passes: otherwise
-    // the compiler keeps this pass's FP64 sums alive through them
-#pragma unroll
-    for (int i = 0; i < 4; ++i) asm volatile("" : "+v"(sq[i]));
-  }
-
-  // FP64 |L^-1 r|^2 contributions of blocks JA .. JZ-1 against L^-1 itself
-  // (rB64: buffer over L^-1, row stride ld), added to s64 (FP64 row order)
-  template <int JA, int JZ>
-  __device__ void fallback_pass(__amdgpu_buffer_rsrc_t rL, double* s64) {
-    constexpr int NQ = JZ - JA;
-    f64x4 acc[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = (f64x4){0.0, 0.0, 0.0, 0.0};
-    const int lrow = l & 15;
-#pragma unroll 1
-    for (int t = 0; t < 4 * JZ; ++t) {
-      const int i = 4 * t + my_k;
-      const double r = resid(t, false);
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        // L^-1[16J + l%16][i], zero above the diagonal and past the fit
-        const int row = 16 * (JA + q) + lrow;
-        if (4 * t <= 16 * (JA + q) + 15) {
-          const double v = __builtin_bit_cast(
-              double, __builtin_amdgcn_raw_buffer_load_b64(rL, (lrow * ld + i) * 8, 16 * (JA + q) * ld * 8, 0));
-          const double bv = (i <= row && row < n) ? v : 0.0;
-          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(r, bv, acc[q], 0, 0, 0);
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) s64[i] += acc[q][i] * acc[q][i];
-  }
-
-  // |L^-1 r|^2 in FP64 against L^-1 itself, rows in the FP32 output order
-  __device__ void fallback() {
-    const __amdgpu_buffer_rsrc_t rL = buffer_of(uni(p.Linv), 16 * JB * ld * (int)sizeof(double));
-    double s64[4] = {0.0, 0.0, 0.0, 0.0};
-    if constexpr (JH < JB) {
-      fallback_pass<0, JH>(rL, s64);
-      fallback_pass<JH, JB>(rL, s64);
-    } else {
-      fallback_pass<0, JB>(rL, s64);
-    }
-    // FP64 product rows are l/16 + 4i; sum the columns, then move row q of
-    // the FP32 order (4 (l/16) + i) from register q/4 of the lanes l/16 = q%4
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double v = s64[i];
-      v += shfl_xor_d(v, 1);
-      v += shfl_xor_d(v, 2);
-      v += shfl_xor_d(v, 4);
-      v += shfl_xor_d(v, 8);
-      s64[i] = v;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int q = 4 * my_k + i;
-      double v = 0.0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const double t = __shfl(s64[k], 16 * (q & 3), 64);
-        v = (q >> 2) == k ? t : v;
-      }
-      sq[i] = v;
-    }
-  }
-};
-
-// k-steps whose FP32 residuals are kept for the later passes (those below the
-// last pass's first block), and the LDS floats they take per wave.
-constexpr int reg32_stored_steps(int JB) { return JB > 12 ? 40 : (JB > 8 ? 2 * JB : 0); }
-constexpr int kReg32Rbuf = reg32_stored_steps(kRegJB) * 64;
-
-template <int JB, int DM>
-__device__ void post16_wave_reg32(const PostArgs& p, int64_t row0, const double* xs, const double* as, float* rbuf,
-                                  double* part_out, int64_t* cnt_out) {
-  static_assert(JB >= 1 && JB <= kRegJB && DM <= kMaxD, "shape");
-  Reg32<JB, DM> R{p, xs, as, rbuf};
-  const int l = threadIdx.x & 63;
-  const int my_k = l >> 4;
-  R.l = l;
-  R.my_k = my_k;
-  row0 = uni(row0);
-  const int d = uni(p.d);
-  R.n = uni(p.n);
-  R.ld = uni(p.ld);
-  const bool nu5 = uni(p.nu2) == 5;
-  R.amp = uni(p.amp);
-  R.c1 = (nu5 ? 2.23606797749978969641 : 1.73205080756887729353) * uni(p.inv_l);
-  R.c2 = nu5 ? 1.0 / 3.0 : 0.0;
-  const int64_t n_valid = uni(p.n_valid), N_pad = uni(p.N_pad);
-  const auto X64 = gptr(uni(p.X64));
-  const auto orig = gptr(uni(p.orig));
-  const auto visited = gptr(uni(p.visited));
-  const auto mu = gptr((float*)uni(p.mu));
-  const auto var = gptr((float*)uni(p.var));
-  DevState* st = uni(p.st);
-  const double mean_y = st->mean_y, jitter = st->jitter;
-  const int64_t my_row = row0 + (l & 15);
-#pragma unroll
-  for (int j = 0; j < DM; ++j) {
-    const double v = X64[(int64_t)(j < d ? j : d - 1) * N_pad + my_row];
-    R.xr[j] = j < d ? v : 0.0;
-  }
-  // nearest observation of the row
-  double best = __builtin_inf();
-  int bi = 0;
-#pragma unroll 1
-  for (int t = 0; t < 4 * JB; ++t) {
-    const int i = 4 * t + my_k;
-    const double s = R.dist2(i);
-    const bool take = i < R.n && s < best;
-    best = take ? s : best;
-    bi = take ? i : bi;
-  }
-#pragma unroll
-  for (int m = 16; m <= 32; m <<= 1) {
-    const double ob = shfl_xor_d(best, m);
-    const int oi = __shfl_xor(bi, m, 64);
-    if (ob < best || (ob == best && oi < bi)) {
-      best = ob;
-      bi = oi;
-    }
-  }
-  R.bi = bi;
-  const double kp = R.kfun(best);
-  R.c = kp / (R.amp + jitter);
-  const double base = R.amp - kp * R.c;
-  R.krow = gptr((const double*)uni(p.K0)) + (int64_t)bi * R.ld;
-  // FP32 B operand of 16 JB column blocks: 2 JB (JB + 1) tiles of 64 lanes
-  R.rB = buffer_of(uni(p.Bpk), 2 * JB * (JB + 1) * 64 * (int)sizeof(float));
-  R.mp = 0.0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) R.sq[i] = 0.0;
-  // column blocks in passes of at most 6: their FP32 and FP64 sums fit in
-  // registers beside the generation at two waves per SIMD
-  if constexpr (JB > 12) {
-    R.template pass<0, 5, 0, true>();
-    R.template pass<5, 10, 20, true>();
-    R.template pass<10, JB, 40, false>();
-  } else if constexpr (JB > 8) {
-    R.template pass<0, JB / 2, 0, true>();
-    R.template pass<JB / 2, JB, 2 * JB, false>();
-  } else {
-    R.template pass<0, JB, 0, false>();
-  }
-  double mp = R.mp;
-  mp += shfl_xor_d(mp, 16);
-  mp += shfl_xor_d(mp, 32);
-  // output register i of lane l: row 4(l/16) + i, column l%16
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    double v = R.sq[i];
-    v += shfl_xor_d(v, 1);
-    v += shfl_xor_d(v, 2);
-    v += shfl_xor_d(v, 4);
-    v += shfl_xor_d(v, 8);
-    R.sq[i] = v;
-  }
-  // the row constant of output row 4 (l/16) + i sits on lane 4 (l/16) + i
-  double base_o[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) base_o[i] = __shfl(base, 4 * my_k + i, 64);
-  bool flag = false;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) flag |= row0 + 4 * my_k + i < n_valid && R.sq[i] > 4.0 * (base_o[i] - R.sq[i]);
-  if (__any(flag)) R.fallback();
-  double part = 0.0;
-  int64_t cnt = 0;
-  if (l < 16 && my_row < n_valid) mu[my_row] = (float)(mean_y + mp);
-  if ((l & 15) == 0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t r = row0 + 4 * my_k + i;
-      if (r < n_valid) {
-        double v = base_o[i] - R.sq[i];
-        v = v > 0.0 ? v : 0.0;
-        const float vf = (float)v;
-        var[r] = vf;
-        if (!(visited && visited[orig[r]])) {
-          part += (double)vf;
-          ++cnt;
-        }
-      }
-    }
-  }
-  part += __shfl_down(part, 16, 64);
-  part += __shfl_down(part, 32, 64);
-  cnt += __shfl_down(cnt, 16, 64);
-  cnt += __shfl_down(cnt, 32, 64);
-  *part_out = part;
-  *cnt_out = cnt;
-}
-
-// LDS bytes of stage_obs for n_pad <= 16 kRegJB.
-constexpr size_t kStageBytes = (size_t)16 * kRegJB * (kObsPitch + 1) * sizeof(double);
 
 // Rows per workgroup and row blocks per wave of the single-session FP64 / FP32
 // posterior: up to 4 waves of 16 rows within 128 KB of LDS.

@@ -9,7 +9,7 @@
 //    returns its memory and admits waiting sessions in arrival order.
 //  - Continuous batching: a scheduler thread gathers the pending requests of
 //    idle sessions (one in flight per session, oldest first) into a launch of
-//    the batched persistent kernel, on whichever of the server's launch
+//    the batched step graph, on whichever of the server's launch
 //    contexts (one stream each) is free.  Requests that arrive while launches
 //    run join the next launch as soon as a context frees up, so launches
 //    overlap on the device.
@@ -395,7 +395,7 @@ bo_status bo_server_create(bo_server** out, const bo_server_config* cfg) {
   if (cfg->streams < 1 || cfg->streams > 8) return set_error(BO_E_INVALID_ARG, "streams must be 1..8");
   if (cfg->hbm_budget == 0) return set_error(BO_E_BUDGET, "memory budget is zero");
   const bo_batch_config& t = cfg->tiles;
-  if ((t.tile_rows != 16 && t.tile_rows != 32) || t.acq_chunk < 2048 || t.acq_chunk % 2048 ||
+  if ((t.post_order != 0 && t.post_order != 1) || t.acq_chunk < 2048 || t.acq_chunk % 2048 ||
       (t.fit_order != 0 && t.fit_order != 1))
     return set_error(BO_E_INVALID_ARG, "bad tile configuration");
   bo_server* srv = new (std::nothrow) bo_server();

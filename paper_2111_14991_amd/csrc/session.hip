@@ -301,7 +301,10 @@ size_t bpk_bytes(int prec, int n_pad) {
     return 4 * M * (M + 1) * 64 * 16 * 2;
   }
   const size_t JB = n_pad / 16;
-  return 2 * JB * (JB + 1) * 64 * (prec == BO_FP64 ? 8 : 4);
+  if (prec == BO_FP64) return 2 * JB * (JB + 1) * 64 * 8;
+  // FP32: FP64 values while n_pad <= kRegMax, FP32 values above
+  const size_t JR = std::min<size_t>(JB, kRegMax / 16);
+  return std::max(2 * JR * (JR + 1) * 64 * 8, 2 * JB * (JB + 1) * 64 * 4);
 }
 
 bool make_layout(const bo_problem& p, Layout* L) {
