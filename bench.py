@@ -241,55 +241,73 @@ def _progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _objective_table(s):
+    """Noise-free objective of every candidate of a session (the simulated
+    evaluations of the serving run read it; Session.observe's noise is applied
+    per evaluation)."""
+    return s.landscape.value(s.grid_index(np.arange(s.N)))
+
+
 class _ServedPool:
     """The serving form's live sessions on one server: each has at most one
     request in flight (BO is sequential), evaluates the EI choice of its last
     result next (closed loop), and retires at 220 observations, when a fresh
-    seeded session takes its place."""
+    seeded session (drawn before the timed runs, `spares`) takes its place."""
 
     RETIRE = 220
 
-    def __init__(self, srv, bo, W, prec, rng, seed=0, sessions=1024):
+    def __init__(self, srv, bo, W, prec, rng, spares, seed=0, sessions=1024):
         self.srv, self.bo, self.W, self.prec, self.rng, self.seed = srv, bo, W, prec, rng, seed
+        self.spares = spares
         self.fresh = 0
         self.slots = []
         for s in W.config_c5_population(seed, sessions):
-            self.slots.append(self._open(s))
+            self.slots.append(self._open(s, _objective_table(s)))
         self.idle = list(range(len(self.slots)))
         self.live = {}
         self.retired = 0
 
-    def _open(self, s):
+    def _open(self, s, f):
         sid = self.srv.open(s.levels, s.obs_idx, s.y, N=s.N, cand=s.cand, invalid=s.invalid, n_max=256,
                             precision=self.prec)
         vis = s.visited().astype(bool)
         pool = np.flatnonzero((s.invalid == 0) & ~vis)
         acq = self.bo.AcqParams(mode=1, mu_s=float(np.mean(s.y[:s.n_init])), var_s_mean=0.0)
-        return {"s": s, "sid": sid, "vis": vis, "n": s.n, "next": int(self.rng.choice(pool)), "acq": acq}
+        return {"s": s, "f": f, "sid": sid, "vis": vis, "n": s.n, "next": int(self.rng.choice(pool)), "acq": acq}
+
+    def _replacement(self):
+        k = self.fresh
+        self.fresh += 1
+        if k < len(self.spares):
+            return self.spares[k]
+        s = self.W.c5_fresh_session(self.seed, k)
+        return s, _objective_table(s)
 
     def submit(self, i, t_arrive):
         c = self.slots[i]
         idx = c["next"]
-        y = float(c["s"].observe(self.rng, np.array([idx]))[0])
+        # the run-time measurement: the objective with its lognormal noise
+        y = float(c["f"][idx] * np.exp(0.02 * self.rng.standard_normal()))
         c["vis"][idx] = True
         c["n"] += 1
         self.live[self.srv.submit(c["sid"], idx, y, True, c["acq"])] = (i, t_arrive)
 
-    def collect(self):
-        """Finished requests: [(latency from submission ms, latency from arrival ms, n_unmasked)]."""
+    def collect(self, timeout_us=0):
+        """Finished requests (from the server's completion queue, waiting up to
+        timeout_us for the first): [(latency from submission ms, latency from
+        arrival ms, n_unmasked)]."""
         out = []
+        got = self.srv.wait_any(1024, int(timeout_us))
         now = time.perf_counter()
-        for t in [t for t in list(self.live) if self.srv.poll(t)]:
+        for t, r, ms in got:
             i, t_arrive = self.live.pop(t)
-            r, ms = self.srv.wait(t)
             assert r.status == 0, r.status
             c = self.slots[i]
             c["next"] = int(r.idx[0])
             out.append((ms, (now - t_arrive) * 1e3, r.n_unmasked))
             if c["n"] >= self.RETIRE:
                 self.srv.close_session(c["sid"])
-                self.slots[i] = self._open(self.W.c5_fresh_session(self.seed, self.fresh))
-                self.fresh += 1
+                self.slots[i] = self._open(*self._replacement())
                 self.retired += 1
             self.idle.append(i)
         return out
@@ -320,7 +338,9 @@ def _served_run(pool, rate, warm, count, rng, limit_s=120.0):
             while pending and pool.idle:
                 i = pool.idle.pop(int(rng.integers(0, len(pool.idle))))
                 pool.submit(i, pending.pop(0))
-        for ms, ms_e2e, u in pool.collect():
+        # wait for a completion until the next arrival is due, at most 200 us
+        wait_us = 200 if rate is None else max(0.0, min(t_next - time.perf_counter(), 2e-4)) * 1e6
+        for ms, ms_e2e, u in pool.collect(wait_us):
             done += 1
             if done == warm:
                 t_meas = time.perf_counter()
@@ -348,9 +368,12 @@ def bench_serving(args, torch, bo, W) -> int:
     prec = args.precision or "fp32"
     rng = np.random.Generator(np.random.PCG64(17))
     warm, count = 1000, int(args.requests)
+    t0 = time.perf_counter()
+    spares = [(s, _objective_table(s)) for s in (W.c5_fresh_session(0, k) for k in range(320))]
+    _progress(f"{len(spares)} replacement sessions drawn in {time.perf_counter() - t0:.1f} s")
     srv = bo.Server(hbm_budget=64 << 30, max_batch=256, streams=3)
     t0 = time.perf_counter()
-    pool = _ServedPool(srv, bo, W, prec, rng)
+    pool = _ServedPool(srv, bo, W, prec, rng, spares)
     t_open = time.perf_counter() - t0
     sat = _served_run(pool, None, warm, count, rng)
     lam = sat["requests_per_s"]
@@ -364,7 +387,7 @@ def bench_serving(args, torch, bo, W) -> int:
     srv.close()
     # forced admission: the same sessions under a 512 MB budget
     srv2 = bo.Server(hbm_budget=512 << 20, max_batch=256, streams=3)
-    pool2 = _ServedPool(srv2, bo, W, prec, np.random.Generator(np.random.PCG64(18)))
+    pool2 = _ServedPool(srv2, bo, W, prec, np.random.Generator(np.random.PCG64(18)), spares)
     st2_open = srv2.stats()
     forced = dict(_served_run(pool2, 0.8 * lam, warm, count, rng), rate_rps=0.8 * lam,
                   sessions_resident_at_open=st2_open["sessions_resident"],

@@ -417,6 +417,14 @@ bo_status bo_server_poll(bo_server* srv, uint64_t ticket, int32_t* done);
  * submission (ms, nullable), and forgets the ticket. */
 bo_status bo_server_wait(bo_server* srv, uint64_t ticket, bo_acq_result* out, double* latency_ms);
 
+/* Completion queue: waits up to timeout_us microseconds (0: not at all) for
+ * a finished request not yet returned, then returns up to `max` of them in
+ * the order they finished: tickets[k], out[k] and latency_ms[k] (nullable)
+ * for k < *count (0 when none finished in time), and forgets those tickets.
+ * Requests taken by bo_server_wait are not returned again. */
+bo_status bo_server_wait_any(bo_server* srv, int32_t max, int32_t timeout_us, uint64_t* tickets,
+                             bo_acq_result* out, double* latency_ms, int32_t* count);
+
 /* Counters and occupancy of the server. */
 bo_status bo_server_stats(bo_server* srv, bo_server_info* out);
 

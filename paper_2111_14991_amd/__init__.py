@@ -129,6 +129,8 @@ _SIGS = {
                                    C.POINTER(C.c_uint64)]),
     "bo_server_poll": (C.c_int, [_VP, C.c_uint64, C.POINTER(C.c_int32)]),
     "bo_server_wait": (C.c_int, [_VP, C.c_uint64, C.POINTER(bo_acq_result), C.POINTER(C.c_double)]),
+    "bo_server_wait_any": (C.c_int, [_VP, C.c_int32, C.c_int32, C.POINTER(C.c_uint64), C.POINTER(bo_acq_result),
+                                     C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "bo_server_stats": (C.c_int, [_VP, C.POINTER(bo_server_info)]),
 }
 
@@ -575,6 +577,18 @@ class Server:
         ms = C.c_double()
         _check(lib().bo_server_wait(self.h, C.c_uint64(ticket), C.byref(r), C.byref(ms)), "bo_server_wait")
         return _result(r), ms.value
+
+    def wait_any(self, max_count: int = 256, timeout_us: int = 1000) -> list:
+        """Finished requests not yet returned, in completion order (waits up
+        to timeout_us for the first): [(ticket, StepResult, latency_ms)]."""
+        if getattr(self, "_cq", None) is None or self._cq[0] < max_count:
+            self._cq = (max_count, (C.c_uint64 * max_count)(), (bo_acq_result * max_count)(),
+                        (C.c_double * max_count)())
+        _, t, r, ms = self._cq
+        k = C.c_int32()
+        _check(lib().bo_server_wait_any(self.h, int(max_count), int(timeout_us), t, r, ms, C.byref(k)),
+               "bo_server_wait_any")
+        return [(int(t[i]), _result(r[i]), float(ms[i])) for i in range(k.value)]
 
     def stats(self) -> dict:
         i = bo_server_info()

@@ -6,7 +6,10 @@
 //  - Memory admission: a session's device state (workspace, observation
 //    arrays, visited mask) is allocated when it fits in the HBM budget; until
 //    then the session waits, and so do its requests.  Closing a session
-//    returns its memory and admits waiting sessions in arrival order.
+//    returns its memory and admits waiting sessions in arrival order.  A
+//    setup thread allocates, uploads and fits admitted sessions and frees
+//    closed ones, outside the scheduler's lock and on streams that do not
+//    wait for the launches, so admissions never stall the launches.
 //  - Continuous batching: a scheduler thread gathers the pending requests of
 //    idle sessions (one in flight per session, oldest first) into a launch of
 //    the batched step graph, on whichever of the server's launch
@@ -56,7 +59,9 @@ struct SrvSession {
   double* y_dev = nullptr;
   uint8_t* vis_dev = nullptr;
   int32_t n = 0;
-  int state = 0;  // 0 waiting for memory, 1 resident, 2 closing, 3 setup failed
+  int state = 0;  // 0 waiting for memory, 1 resident, 2 closing, 3 setup failed, 4 being set up
+  bool close_requested = false;  // closed while being set up
+  bool reserved = false;         // its bytes are counted in the server's `used`
   bool busy = false;
   bool need_refit = false;
   int32_t setup_status = BO_OK;
@@ -87,11 +92,23 @@ size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 }  // namespace
 
 struct bo_server {
+  struct Freed {
+    void* dev;
+    bo_session* s;
+    size_t bytes;
+  };
   bo_server_config cfg{};
   int device = 0;
   std::mutex mu;
-  std::condition_variable cv_work;  // new requests / sessions / stop
-  std::condition_variable cv_done;  // results / admissions
+  std::condition_variable cv_work;   // new requests / sessions / stop
+  std::condition_variable cv_done;   // results / admissions
+  std::condition_variable cv_setup;  // sessions to set up / memory to free / stop
+  std::deque<int32_t> setup_q;       // admitted sessions (state 4) to set up
+  std::vector<Freed> free_q;         // memory of closed sessions, still counted in `used`
+  std::deque<uint64_t> completed;    // finished tickets, in order of completion
+  std::vector<hipStream_t> launch_streams;
+  void* staging = nullptr;           // setup thread's device staging buffer
+  size_t staging_bytes = 0;
   std::map<int32_t, std::unique_ptr<SrvSession>> sessions;
   std::deque<int32_t> waiting;      // sessions waiting for memory, in arrival order
   std::map<uint64_t, Request> reqs;
@@ -104,6 +121,7 @@ struct bo_server {
   uint64_t next_ticket = 1;
   bool stop = false;
   std::thread worker;
+  std::thread setup_worker;
   int64_t steps_done = 0, n_launches = 0, items_launched = 0;
 };
 
@@ -116,28 +134,41 @@ size_t session_bytes(const bo_problem& p, size_t* ws) {
   return a256(w) + a256(sizeof(int64_t) * p.n_max) + a256(sizeof(double) * p.n_max) + a256((size_t)p.N);
 }
 
+// Frees a session's device state at once (server teardown).
 void free_session_memory(bo_server* srv, SrvSession* ss) {
   if (ss->s) bo_session_destroy(ss->s);
   ss->s = nullptr;
-  if (ss->dev) {
-    (void)hipFree(ss->dev);
-    srv->used -= ss->bytes;
-  }
+  if (ss->dev) (void)hipFree(ss->dev);
   ss->dev = nullptr;
+  if (ss->reserved) srv->used -= ss->bytes;
+  ss->reserved = false;
+}
+
+// Hands a session's device state and its reserved bytes to the setup thread,
+// which frees the memory and then returns the bytes to the budget.  Lock held.
+void defer_free(bo_server* srv, SrvSession* ss) {
+  if (ss->s || ss->dev || ss->reserved) {
+    srv->free_q.push_back(bo_server::Freed{ss->dev, ss->s, ss->reserved ? ss->bytes : 0});
+    srv->cv_setup.notify_all();
+  }
+  ss->s = nullptr;
+  ss->dev = nullptr;
+  ss->reserved = false;
 }
 
 // Allocates and initializes a session's device state (the candidate set, the
-// initial observations and their fit).  Called with the server lock held.
+// initial observations and their fit) on the setup stream.  Runs on the setup
+// thread without the server lock: nothing else touches the session while it
+// is being set up (state 4).
 int32_t setup_session(bo_server* srv, SrvSession* ss) {
   size_t ws = 0;
   session_bytes(ss->prob, &ws);
-  hipError_t e = hipSetDevice(srv->device);
-  if (e == hipSuccess) e = hipMalloc(&ss->dev, ss->bytes);
+  hipStream_t st = srv->setup_stream;
+  hipError_t e = hipMalloc(&ss->dev, ss->bytes);
   if (e != hipSuccess) {
     ss->dev = nullptr;
     return set_error(BO_E_HIP, "session memory: %s", hipGetErrorString(e));
   }
-  srv->used += ss->bytes;
   unsigned char* p = (unsigned char*)ss->dev;
   void* wsp = p;
   p += a256(ws);
@@ -146,36 +177,37 @@ int32_t setup_session(bo_server* srv, SrvSession* ss) {
   ss->y_dev = (double*)p;
   p += a256(sizeof(double) * ss->prob.n_max);
   ss->vis_dev = (uint8_t*)p;
-  bo_status rc = bo_session_create(&ss->s, &ss->prob, &ss->gp, wsp, ws, srv->setup_stream);
+  bo_status rc = bo_session_create(&ss->s, &ss->prob, &ss->gp, wsp, ws, st);
   if (rc != BO_OK) return rc;
-  // candidate list and restriction mask go through the visited array's space
-  // and a temporary buffer; the visited mask is written afterwards
+  // candidate list through the setup thread's staging buffer, restriction
+  // mask through the visited array's space; the visited mask is written after
   const int64_t N = ss->prob.N;
-  void* tmp = nullptr;
-  const size_t tmp_bytes = (ss->cand.empty() ? 0 : sizeof(int64_t) * N);
-  if (tmp_bytes) {
-    e = hipMalloc(&tmp, tmp_bytes);
+  const size_t cand_bytes = ss->cand.empty() ? 0 : sizeof(int64_t) * N;
+  if (cand_bytes > srv->staging_bytes) {
+    if (srv->staging) (void)hipFree(srv->staging);
+    srv->staging = nullptr;
+    srv->staging_bytes = 0;
+    e = hipMalloc(&srv->staging, cand_bytes);
     if (e != hipSuccess) return set_error(BO_E_HIP, "staging: %s", hipGetErrorString(e));
-    e = hipMemcpy(tmp, ss->cand.data(), tmp_bytes, hipMemcpyHostToDevice);
+    srv->staging_bytes = cand_bytes;
   }
+  e = hipSuccess;
+  if (cand_bytes) e = hipMemcpyAsync(srv->staging, ss->cand.data(), cand_bytes, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !ss->invalid.empty())
-    e = hipMemcpy(ss->vis_dev, ss->invalid.data(), (size_t)N, hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    if (tmp) (void)hipFree(tmp);
-    return set_error(BO_E_HIP, "staging copy: %s", hipGetErrorString(e));
-  }
-  rc = bo_set_grid(ss->s, ss->levels.data(), (const int64_t*)tmp, ss->invalid.empty() ? nullptr : ss->vis_dev,
-                   nullptr);
-  if (tmp) (void)hipFree(tmp);
+    e = hipMemcpyAsync(ss->vis_dev, ss->invalid.data(), (size_t)N, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return set_error(BO_E_HIP, "staging copy: %s", hipGetErrorString(e));
+  rc = bo_set_grid(ss->s, ss->levels.data(), cand_bytes ? (const int64_t*)srv->staging : nullptr,
+                   ss->invalid.empty() ? nullptr : ss->vis_dev, nullptr);
   if (rc != BO_OK) return rc;
   std::vector<uint8_t> vis((size_t)N, 0);
   for (int64_t i : ss->obs0)
     if (i >= 0 && i < N) vis[(size_t)i] = 1;
-  e = hipMemcpy(ss->vis_dev, vis.data(), (size_t)N, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(ss->obs_dev, ss->obs0.data(), sizeof(int64_t) * ss->obs0.size(),
-                                     hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(ss->y_dev, ss->y0.data(), sizeof(double) * ss->y0.size(),
-                                     hipMemcpyHostToDevice);
+  e = hipMemcpyAsync(ss->vis_dev, vis.data(), (size_t)N, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ss->obs_dev, ss->obs0.data(), sizeof(int64_t) * ss->obs0.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ss->y_dev, ss->y0.data(), sizeof(double) * ss->y0.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host vectors go out of scope below
   if (e != hipSuccess) return set_error(BO_E_HIP, "initial observations: %s", hipGetErrorString(e));
   ss->n = (int32_t)ss->obs0.size();
   rc = bo_gp_fit(ss->s, ss->obs_dev, ss->y_dev, ss->n);
@@ -192,7 +224,8 @@ int32_t setup_session(bo_server* srv, SrvSession* ss) {
   return BO_OK;
 }
 
-// Admits waiting sessions in arrival order while they fit.  Lock held.
+// Admits waiting sessions in arrival order while they fit: their memory is
+// reserved and the setup thread sets them up.  Lock held.
 void admit(bo_server* srv) {
   while (!srv->waiting.empty()) {
     auto it = srv->sessions.find(srv->waiting.front());
@@ -203,14 +236,51 @@ void admit(bo_server* srv) {
     SrvSession* ss = it->second.get();
     if (srv->used + ss->bytes > srv->cfg.hbm_budget) break;
     srv->waiting.pop_front();
+    srv->used += ss->bytes;
+    ss->reserved = true;
+    ss->state = 4;
+    srv->setup_q.push_back(ss->id);
+    srv->cv_setup.notify_all();
+  }
+}
+
+void setup_main(bo_server* srv) {
+  (void)hipSetDevice(srv->device);
+  std::unique_lock<std::mutex> lk(srv->mu);
+  for (;;) {
+    srv->cv_setup.wait(lk, [&] { return srv->stop || !srv->setup_q.empty() || !srv->free_q.empty(); });
+    if (srv->stop) break;
+    if (!srv->free_q.empty()) {
+      std::vector<bo_server::Freed> f;
+      f.swap(srv->free_q);
+      lk.unlock();
+      for (auto& x : f) {
+        if (x.s) bo_session_destroy(x.s);
+        if (x.dev) (void)hipFree(x.dev);
+      }
+      lk.lock();
+      for (auto& x : f) srv->used -= x.bytes;
+      admit(srv);
+      srv->cv_work.notify_all();
+      continue;
+    }
+    const int32_t id = srv->setup_q.front();
+    srv->setup_q.pop_front();
+    auto it = srv->sessions.find(id);
+    if (it == srv->sessions.end()) continue;
+    SrvSession* ss = it->second.get();
+    lk.unlock();
     const int32_t rc = setup_session(srv, ss);
+    lk.lock();
     if (rc != BO_OK) {
-      free_session_memory(srv, ss);
+      defer_free(srv, ss);
       ss->state = 3;
       ss->setup_status = rc;
     } else {
       ss->state = 1;
     }
+    if (ss->close_requested) ss->state = 2;
+    srv->cv_work.notify_all();
     srv->cv_done.notify_all();
   }
 }
@@ -226,6 +296,7 @@ void fail_request(bo_server* srv, uint64_t t, int32_t status) {
   r.res = z;
   r.done = true;
   r.t_done = Clock::now();
+  srv->completed.push_back(t);
 }
 
 // Collects finished launches.  Lock held.
@@ -243,6 +314,7 @@ void retire(bo_server* srv) {
       if (rc != BO_OK) r.res.status = rc;
       r.done = true;
       r.t_done = now;
+      srv->completed.push_back(L->tickets[i]);
       ss->busy = false;
       const int32_t st = r.res.status;
       if (r.valid) {
@@ -272,7 +344,7 @@ void retire(bo_server* srv) {
           break;
         }
     if (ss->state == 2 && !ss->busy && !queued) {
-      free_session_memory(srv, ss);
+      defer_free(srv, ss);
       it = srv->sessions.erase(it);
     } else {
       ++it;
@@ -403,27 +475,39 @@ bo_status bo_server_create(bo_server** out, const bo_server_config* cfg) {
   srv->cfg = *cfg;
   hipError_t e = hipGetDevice(&srv->device);
   const size_t per = a256(BatchCtx::bytes(cfg->max_batch));
+  // streams that do not wait for the null stream (nor it for them), so that
+  // session setup and teardown never hold up the launches
   if (e == hipSuccess) e = hipMalloc(&srv->ctx_mem, per * cfg->streams);
-  if (e == hipSuccess) e = hipStreamCreate(&srv->setup_stream);
-  if (e != hipSuccess) {
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&srv->setup_stream, hipStreamNonBlocking);
+  for (int i = 0; e == hipSuccess && i < cfg->streams; ++i) {
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) srv->launch_streams.push_back(st);
+  }
+  auto undo = [&]() {
+    for (auto& M : srv->launches) M->ctx.destroy();
+    for (hipStream_t st : srv->launch_streams) (void)hipStreamDestroy(st);
+    if (srv->setup_stream) (void)hipStreamDestroy(srv->setup_stream);
     if (srv->ctx_mem) (void)hipFree(srv->ctx_mem);
     delete srv;
-    return set_error(BO_E_HIP, "server create: %s", hipGetErrorString(e));
+  };
+  if (e != hipSuccess) {
+    const char* msg = hipGetErrorString(e);
+    undo();
+    return set_error(BO_E_HIP, "server create: %s", msg);
   }
   for (int i = 0; i < cfg->streams; ++i) {
     std::unique_ptr<Launch> L(new Launch());
-    bo_status rc = L->ctx.init(cfg->max_batch, (unsigned char*)srv->ctx_mem + per * i, per, nullptr);
+    bo_status rc = L->ctx.init(cfg->max_batch, (unsigned char*)srv->ctx_mem + per * i, per, srv->launch_streams[i]);
     if (rc != BO_OK) {
       L->ctx.destroy();
-      for (auto& M : srv->launches) M->ctx.destroy();
-      (void)hipFree(srv->ctx_mem);
-      (void)hipStreamDestroy(srv->setup_stream);
-      delete srv;
+      undo();
       return rc;
     }
     srv->launches.push_back(std::move(L));
   }
   srv->worker = std::thread(worker_main, srv);
+  srv->setup_worker = std::thread(setup_main, srv);
   *out = srv;
   return BO_OK;
 }
@@ -435,9 +519,17 @@ void bo_server_destroy(bo_server* srv) {
     srv->stop = true;
   }
   srv->cv_work.notify_all();
+  srv->cv_setup.notify_all();
   srv->worker.join();
+  srv->setup_worker.join();
+  for (auto& x : srv->free_q) {
+    if (x.s) bo_session_destroy(x.s);
+    if (x.dev) (void)hipFree(x.dev);
+  }
   for (auto& kv : srv->sessions) free_session_memory(srv, kv.second.get());
   for (auto& L : srv->launches) L->ctx.destroy();
+  for (hipStream_t st : srv->launch_streams) (void)hipStreamDestroy(st);
+  if (srv->staging) (void)hipFree(srv->staging);
   (void)hipFree(srv->ctx_mem);
   (void)hipStreamDestroy(srv->setup_stream);
   delete srv;
@@ -490,6 +582,8 @@ bo_status bo_server_close(bo_server* srv, int32_t id) {
                        srv->pending.end());
     srv->sessions.erase(it);
     srv->cv_done.notify_all();
+  } else if (ss->state == 4) {
+    ss->close_requested = true;  // closed once its setup ends
   } else {
     ss->state = 2;  // its queued steps still run; memory is freed once idle
   }
@@ -505,7 +599,8 @@ bo_status bo_server_submit(bo_server* srv, int32_t id, int64_t idx, double y, in
   if (rc != BO_OK) return rc;
   std::lock_guard<std::mutex> lk(srv->mu);
   auto it = srv->sessions.find(id);
-  if (it == srv->sessions.end() || it->second->state == 2) return set_error(BO_E_INVALID_ARG, "no open session %d", id);
+  if (it == srv->sessions.end() || it->second->state == 2 || it->second->close_requested)
+    return set_error(BO_E_INVALID_ARG, "no open session %d", id);
   if (idx < 0 || idx >= it->second->prob.N) return set_error(BO_E_INVALID_ARG, "index %lld out of range", (long long)idx);
   if (valid && !std::isfinite(y)) return set_error(BO_E_INVALID_ARG, "y is not finite");
   Request r;
@@ -545,6 +640,41 @@ bo_status bo_server_wait(bo_server* srv, uint64_t ticket, bo_acq_result* out, do
   return BO_OK;
 }
 
+bo_status bo_server_wait_any(bo_server* srv, int32_t max, int32_t timeout_us, uint64_t* tickets,
+                             bo_acq_result* out, double* latency_ms, int32_t* count) {
+  if (!srv || !tickets || !out || !count) return set_error(BO_E_INVALID_ARG, "NULL argument");
+  if (max < 1) return set_error(BO_E_INVALID_ARG, "max must be >= 1");
+  if (timeout_us < 0) return set_error(BO_E_INVALID_ARG, "timeout must be >= 0");
+  *count = 0;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  // tickets already taken by bo_server_wait are gone from the table
+  auto drop_taken = [&] {
+    while (!srv->completed.empty() && srv->reqs.find(srv->completed.front()) == srv->reqs.end())
+      srv->completed.pop_front();
+  };
+  drop_taken();
+  if (srv->completed.empty() && timeout_us > 0)
+    srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), [&] {
+      drop_taken();
+      return !srv->completed.empty();
+    });
+  int32_t k = 0;
+  while (k < max && !srv->completed.empty()) {
+    const uint64_t t = srv->completed.front();
+    srv->completed.pop_front();
+    auto it = srv->reqs.find(t);
+    if (it == srv->reqs.end()) continue;
+    tickets[k] = t;
+    out[k] = it->second.res;
+    if (latency_ms)
+      latency_ms[k] = std::chrono::duration<double, std::milli>(it->second.t_done - it->second.t_submit).count();
+    srv->reqs.erase(it);
+    ++k;
+  }
+  *count = k;
+  return BO_OK;
+}
+
 bo_status bo_server_stats(bo_server* srv, bo_server_info* out) {
   if (!srv || !out) return set_error(BO_E_INVALID_ARG, "NULL argument");
   std::lock_guard<std::mutex> lk(srv->mu);
@@ -554,7 +684,7 @@ bo_status bo_server_stats(bo_server* srv, bo_server_info* out) {
   s.mean_batch = srv->n_launches ? (double)srv->items_launched / (double)srv->n_launches : 0.0;
   s.bytes_in_use = srv->used;
   for (auto& kv : srv->sessions) {
-    if (kv.second->state == 1 || kv.second->state == 2) ++s.sessions_resident;
+    if (kv.second->state == 1 || kv.second->state == 2 || kv.second->state == 4) ++s.sessions_resident;
     else if (kv.second->state == 0) ++s.sessions_waiting;
   }
   s.pending = (int64_t)srv->pending.size();

@@ -99,7 +99,17 @@ def test_server_mix_equals_alone(bo):
             reqs.append((i, idx, y, valid))
         # one burst: more requests than a launch holds, so launches queue and overlap
         tickets = [srv.submit(sids[i], idx, y, valid, acqs[i]) for i, idx, y, valid in reqs]
-        got = [srv.wait(t) for t in tickets]
+        if rnd % 2 == 0:
+            got = [srv.wait(t) for t in tickets]
+        else:
+            # through the completion queue, a few at a time
+            done = {}
+            while len(done) < len(tickets):
+                for t, r, ms in srv.wait_any(3, 100000):
+                    assert t in tickets and t not in done
+                    done[t] = (r, ms)
+            got = [done[t] for t in tickets]
+            assert srv.wait_any(4, 0) == []
         for (i, idx, y, valid), (rm, ms) in zip(reqs, got):
             assert ms > 0.0
             _same(rm, alone[i].step(idx, y, valid, acqs[i]))
