@@ -29,7 +29,7 @@ struct BatchItem {
   uint8_t* mark;           // device, nullable: mark[new_idx] = 1 before the fit
 };
 
-constexpr int kBatchNodes = 6;  // fits, posterior FP64 and FP32, exploration factors, chunks, selections
+constexpr int kBatchNodes = 6;  // fits, posterior (two classes), exploration factors, chunks, selections
 
 class BatchCtx {
  public:

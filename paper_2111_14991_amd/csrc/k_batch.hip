@@ -2,14 +2,15 @@
 // dimensions and observation counts) advance one step in one captured HIP
 // graph, replayed every step:
 //
-//   plan copy -> fits -> posterior (FP64, FP32) -> exploration factors ->
+//   plan copy -> fits -> posterior (d <= 8, d > 8) -> exploration factors ->
 //   acquisition chunks -> selections -> result copy.
 //
 //  - fits: one workgroup per session (FP64, fit_small_run or append_run,
 //    n <= 256), largest first when the plan asks for it;
-//  - posterior: one launch per precision over every session's 64-candidate
-//    slots, one slot per workgroup, by default the sessions of the costliest
-//    slots first (longest first keeps the tail short).  Each slot is the
+//  - posterior: one launch per coordinate class (d <= 8, d > 8) over every
+//    session's 64-candidate slots, FP64 and FP32 sessions alike, one slot per
+//    workgroup, by default the sessions of the costliest slots first (longest
+//    first keeps the tail short).  Each slot is the
 //    single-session kernel's workgroup (four waves of 16 rows in the
 //    register-resident posterior, their partials added in wave order), with
 //    the session's shape chosen at run time from specialised, inlined bodies;
@@ -63,13 +64,13 @@ struct BatchSession {
 struct PlanHdr {
   int32_t count;
   int32_t pad0;
-  uint32_t wg_post[2];        // posterior workgroups (slots), FP64 and FP32
+  uint32_t wg_post[2];        // posterior workgroups (slots), d <= 8 and d > 8
   uint32_t wg_acq;            // acquisition workgroups
   uint32_t pad[3];
 };
 
 // Plan layout: PlanHdr | BatchSession[cap] | fit order[cap] |
-// per precision q (FP64, FP32): session list[cap], workgroup offsets[cap + 1] |
+// per class q (d <= 8, d > 8): session list[cap], workgroup offsets[cap + 1] |
 // acquisition offsets[cap + 1]
 struct PlanView {
   PlanHdr* hdr;
@@ -131,12 +132,15 @@ __global__ __launch_bounds__(kSmallThreads) void k_bfit(unsigned char* plan, int
   else if (S.fit_kind == 1) append_run(S.fit, s_raw);
 }
 
-// Posterior of one precision: workgroup g takes one slot of one session,
+// Posterior of the sessions of one class (DM = 8: d <= 8; DM = kMaxD: the
+// others), both precisions: workgroup g takes one slot of one session,
 // computed as the single-session kernel's workgroup does (k_post16r: same
-// bodies, same order of the four waves' partials), and
-// publishes it in the session's slot array.  (A loop over several slots per
-// workgroup costs the shape bodies their spill-free register allocation.)
-template <bool F32>
+// bodies, same order of the four waves' partials; the class only sets how
+// many coordinates the distance loop runs over, and the zero coordinates
+// past d add exact zeros), and publishes it in the session's slot array.  (A
+// loop over several slots per workgroup, or both classes in one kernel, costs
+// the shape bodies their spill-free register allocation.)
+template <int DM>
 __global__ __launch_bounds__(kSlotThreads) __attribute__((amdgpu_waves_per_eu(2))) void k_bpost(
     unsigned char* plan, int cap) {
   __shared__ double s_xo[16 * kRegJB * kObsPitch];
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(kSlotThreads) __attribute__((amdgpu_waves_per_eu(2)
   __shared__ double s_wsum[4];
   __shared__ int64_t s_wcnt[4];
   const PlanView v = plan_view(plan, cap);
-  constexpr int q = F32 ? 1 : 0;
+  constexpr int q = DM == 8 ? 0 : 1;
   if (blockIdx.x >= v.hdr->wg_post[q]) return;  // an empty list still launches one workgroup
   const int k = find_owner(v.off[q], v.hdr->count, blockIdx.x);
   const BatchSession& S = v.ses[v.list[q][k]];
@@ -152,22 +156,20 @@ __global__ __launch_bounds__(kSlotThreads) __attribute__((amdgpu_waves_per_eu(2)
   if (p.st->status != BO_OK) return;
   const int slot = (int)(blockIdx.x - v.off[q][k]);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  stage_obs(p, s_xo, s_alpha);
-  // shape key: n_pad / 16 (4, 8, 12 or 16) and whether d <= 8
-  const int key = (p.n_pad >> 4) * 2 + (p.d <= 8 ? 0 : 1);
+  const int jb = reg_jb(p.n);
+  stage_obs(p, 16 * jb, s_xo, s_alpha);
   {
     const int64_t row0 = ((int64_t)slot * 4 + w) * 16;
     double part;
     int64_t cnt;
-    switch (key) {
-      case 8: post16_wave_reg<4, 8, F32>(p, row0, s_xo, s_alpha, &part, &cnt); break;
-      case 9: post16_wave_reg<4, kMaxD, F32>(p, row0, s_xo, s_alpha, &part, &cnt); break;
-      case 16: post16_wave_reg<8, 8, F32>(p, row0, s_xo, s_alpha, &part, &cnt); break;
-      case 17: post16_wave_reg<8, kMaxD, F32>(p, row0, s_xo, s_alpha, &part, &cnt); break;
-      case 24: post16_wave_reg<12, 8, F32>(p, row0, s_xo, s_alpha, &part, &cnt); break;
-      case 25: post16_wave_reg<12, kMaxD, F32>(p, row0, s_xo, s_alpha, &part, &cnt); break;
-      case 32: post16_wave_reg<16, 8, F32>(p, row0, s_xo, s_alpha, &part, &cnt); break;
-      default: post16_wave_reg<16, kMaxD, F32>(p, row0, s_xo, s_alpha, &part, &cnt); break;
+    switch (jb) {
+#define BO_REG_CASE(J) \
+  case J: post16_wave_reg<J, DM>(p, row0, s_xo, s_alpha, &part, &cnt); break;
+      BO_REG_CASE(1) BO_REG_CASE(2) BO_REG_CASE(3) BO_REG_CASE(4) BO_REG_CASE(5) BO_REG_CASE(6)
+      BO_REG_CASE(7) BO_REG_CASE(8) BO_REG_CASE(9) BO_REG_CASE(10) BO_REG_CASE(11) BO_REG_CASE(12)
+      BO_REG_CASE(13) BO_REG_CASE(14) BO_REG_CASE(15)
+#undef BO_REG_CASE
+      default: post16_wave_reg<16, DM>(p, row0, s_xo, s_alpha, &part, &cnt); break;
     }
     if (l == 0) {
       s_wsum[w] = part;
@@ -342,20 +344,20 @@ bo_status BatchCtx::build_plan(const BatchItem* items, int count, const bo_batch
     std::stable_sort(order_scratch.begin(), order_scratch.end(),
                      [&](int a, int c) { return items[a].n > items[c].n; });
   for (int i = 0; i < count; ++i) v.order[i] = order_scratch[i];
-  // posterior lists: the sessions of the costliest slots (largest n_pad)
-  // first, or in the fit order
+  // posterior lists, by coordinate class (d <= 8, d > 8): the sessions of the
+  // costliest slots (most column blocks) first, or in the fit order
   for (int q = 0; q < 2; ++q) {
     int k = 0;
     uint32_t wg = 0;
     for (int i = 0; i < count; ++i) {
       const BatchSession& B = v.ses[order_scratch[i]];
-      if (B.f32 != q) continue;
+      if ((B.post.d > 8 ? 1 : 0) != q) continue;
       v.list[q][k] = order_scratch[i];
       ++k;
     }
     if (cfg.post_order == 0)
       std::stable_sort(v.list[q], v.list[q] + k,
-                       [&](int a, int c) { return v.ses[a].post.n_pad > v.ses[c].post.n_pad; });
+                       [&](int a, int c) { return reg_jb(v.ses[a].post.n) > reg_jb(v.ses[c].post.n); });
     for (int j = 0; j < k; ++j) {
       v.off[q][j] = wg;
       wg += (uint32_t)v.ses[v.list[q][j]].n_slots;
@@ -386,8 +388,8 @@ struct BatchKernel {
 static const BatchKernel* batch_kernels() {
   static const BatchKernel k[kBatchNodes] = {
       {(const void*)k_bfit, (unsigned)kSmallThreads, (unsigned)kFitLds},
-      {(const void*)k_bpost<false>, (unsigned)kSlotThreads, 0u},
-      {(const void*)k_bpost<true>, (unsigned)kSlotThreads, 0u},
+      {(const void*)k_bpost<8>, (unsigned)kSlotThreads, 0u},
+      {(const void*)k_bpost<kMaxD>, (unsigned)kSlotThreads, 0u},
       {(const void*)k_blam, (unsigned)kSlotThreads, 0u},
       {(const void*)k_bacq, (unsigned)kAcqThreads, 0u},
       {(const void*)k_bsel, (unsigned)kAcqThreads, 0u},

@@ -43,10 +43,11 @@ __global__ __launch_bounds__(256) void k_post16(PostArgs p) {
   if (last_block(&p.st->ticket_post, &s_last)) finish_lambda(p, gridDim.x, s_rsum, s_rcnt, blockDim.x);
 }
 
-// FP64 posterior with register-resident accumulators, n_pad = 16 JB <= 256,
-// d <= DM: four waves of 16 candidates per workgroup, no LDS operand; OUT32:
-// the FP32 mode (FP32 mean and variance from the same FP64 products).
-template <int JB, int DM, bool OUT32>
+// FP64 posterior with register-resident accumulators, JB = reg_jb(n) <= 16,
+// d <= DM: four waves of 16 candidates per workgroup, no LDS operand (the
+// FP64 mode, and the FP32 mode's FP32 mean and variance from the same FP64
+// products).
+template <int JB, int DM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_post16r(PostArgs p) {
   __shared__ double s_wsum[4];
   __shared__ int64_t s_wcnt[4];
@@ -58,10 +59,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   if (p.st->status != BO_OK) return;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * 16;
-  stage_obs(p, s_xo, s_alpha);
+  stage_obs(p, 16 * JB, s_xo, s_alpha);
   double part;
   int64_t cnt;
-  post16_wave_reg<JB, DM, OUT32>(p, row0, s_xo, s_alpha, &part, &cnt);
+  post16_wave_reg<JB, DM>(p, row0, s_xo, s_alpha, &part, &cnt);
   if (l == 0) {
     s_wsum[w] = part;
     s_wcnt[w] = cnt;
@@ -80,12 +81,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
   if (last_block(&p.st->ticket_post, &s_last)) finish_lambda(p, gridDim.x, s_rsum, s_rcnt, blockDim.x);
 }
 
-template <int JB, bool OUT32>
+template <int JB>
 static void launch_post16r(const PostArgs& a, int grid, hipStream_t st) {
   if (a.d <= 8)
-    hipLaunchKernelGGL((k_post16r<JB, 8, OUT32>), dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_post16r<JB, 8>), dim3(grid), dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL((k_post16r<JB, kMaxD, OUT32>), dim3(grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((k_post16r<JB, kMaxD>), dim3(grid), dim3(256), 0, st, a);
 }
 
 int post16_rows_per_block(int prec, int n_pad) { return 16 * post16_waves(prec, n_pad); }
@@ -99,12 +100,13 @@ hipError_t launch_posterior(const DevPtrs& P, const Layout& Lo, const GpConst& g
   if (a.n_pad <= 16 * kRegJB) {
     int grid = (int)((n_valid + 63) / 64);
     grid = grid > 0 ? grid : 1;
-    const bool f64 = Lo.prec == BO_FP64;
-    switch (a.n_pad >> 4) {  // n_pad is a multiple of 64
-      case 4: f64 ? launch_post16r<4, false>(a, grid, st) : launch_post16r<4, true>(a, grid, st); break;
-      case 8: f64 ? launch_post16r<8, false>(a, grid, st) : launch_post16r<8, true>(a, grid, st); break;
-      case 12: f64 ? launch_post16r<12, false>(a, grid, st) : launch_post16r<12, true>(a, grid, st); break;
-      case 16: f64 ? launch_post16r<16, false>(a, grid, st) : launch_post16r<16, true>(a, grid, st); break;
+    switch (reg_jb(a.n)) {
+#define BO_REG_CASE(J) \
+  case J: launch_post16r<J>(a, grid, st); break;
+      BO_REG_CASE(1) BO_REG_CASE(2) BO_REG_CASE(3) BO_REG_CASE(4) BO_REG_CASE(5) BO_REG_CASE(6)
+      BO_REG_CASE(7) BO_REG_CASE(8) BO_REG_CASE(9) BO_REG_CASE(10) BO_REG_CASE(11) BO_REG_CASE(12)
+      BO_REG_CASE(13) BO_REG_CASE(14) BO_REG_CASE(15) BO_REG_CASE(16)
+#undef BO_REG_CASE
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -2,8 +2,6 @@
 // the FP64 / FP32 modes, and the last-workgroup reduction of the mean variance
 // and the exploration factor.
 #pragma once
-#include <type_traits>
-
 #include "bo_internal.h"
 #include "bo_device.h"
 
@@ -11,6 +9,7 @@ namespace bo {
 
 struct PostArgs {
   int n, n_pad, d, nu2;
+  int out32;  // mean and variance stored in FP32 (the FP32 mode)
   int ld;  // row stride of K0
   double inv_l, amp;
   int64_t n_valid, N_pad;
@@ -431,24 +430,29 @@ __device__ void post16_wave(const PostArgs& p, int64_t row0, double* kt, double*
 constexpr int kRegJB = kRegMax / 16;  // n_pad <= kRegMax takes the register-resident posterior
 constexpr int kObsPitch = kMaxD + 1;  // LDS row pitch of the staged observations
 
-// Stages the observation coordinates (n_pad rows, pitch kObsPitch, zero past
-// the d-th) and alpha (n_pad, zero past n) of a fit into LDS for
-// post16_wave_reg; every thread of the workgroup calls it.  The odd pitch puts
-// the four observations a wave reads at once in different banks.
-__device__ inline void stage_obs(const PostArgs& p, double* xs, double* as) {
-  for (int e = threadIdx.x; e < p.n_pad * kObsPitch; e += blockDim.x) {
+// Observations of the register-resident posterior: n rounded up to 16
+// (16 jb, jb = 1 .. kRegJB column blocks; the blocks and k-steps of the
+// 64-padded layout beyond them hold zeros only and are skipped).
+__host__ __device__ inline int reg_jb(int n) { return (n + 15) >> 4; }
+
+// Stages the observation coordinates (`rows` = 16 jb rows, pitch kObsPitch,
+// zero past the d-th) and alpha (zero past n) of a fit into LDS for
+// post16_wave_reg; every thread of the workgroup calls it.  The odd pitch
+// puts the four observations a wave reads at once in different banks.
+__device__ inline void stage_obs(const PostArgs& p, int rows, double* xs, double* as) {
+  for (int e = threadIdx.x; e < rows * kObsPitch; e += blockDim.x) {
     const int i = e / kObsPitch, j = e - i * kObsPitch;
     const double v = p.Xo64[i * kMaxD + (j < kMaxD ? j : kMaxD - 1)];
     xs[e] = j < p.d ? v : 0.0;
   }
-  for (int i = threadIdx.x; i < p.n_pad; i += blockDim.x) {
+  for (int i = threadIdx.x; i < rows; i += blockDim.x) {
     const double v = p.alpha[i];
     as[i] = i < p.n ? v : 0.0;
   }
   __syncthreads();
 }
 
-// FP64 posterior of 16 candidates by one wave for n_pad = 16 JB, with the
+// FP64 posterior of 16 candidates by one wave for JB = reg_jb(n), with the
 // contraction in k-outer order: lane l generates its A element
 // k*(row l%16, observation 4t + l/16) once per k-step t and feeds it to every
 // column block J >= t/4 (the others are zero above the diagonal), whose
@@ -456,11 +460,11 @@ __device__ inline void stage_obs(const PostArgs& p, double* xs, double* as) {
 // as stage_obs leaves them; the candidate's first DM coordinates (DM >= d)
 // from HBM.  The shape is a template parameter, so every step is
 // straight-line code: the B loads of its live blocks, the kernel value, their
-// MFMAs.  Same outputs and slot partial as post16_wave<false>.  OUT32: the
-// FP32 mode, whose mean and variance are stored in FP32 (its products stay
-// FP64: an FP32 contraction cannot hold the variance to 1e-6 of itself where
-// it is small next to the prior, which is most of a well-sampled space).
-template <int JB, int DM, bool OUT32 = false>
+// MFMAs.  Same outputs and slot partial as post16_wave<false>.  The FP32
+// mode (p.out32) stores the mean and variance in FP32; its products stay FP64:
+// an FP32 contraction cannot hold the variance to 1e-6 of itself where it is
+// small next to the prior, which is most of a well-sampled space.
+template <int JB, int DM>
 __device__ void post16_wave_reg(const PostArgs& p, int64_t row0, const double* xs, const double* as,
                                 double* part_out, int64_t* cnt_out) {
   static_assert(JB >= 1 && JB <= kRegJB && DM <= kMaxD, "shape");
@@ -479,9 +483,9 @@ __device__ void post16_wave_reg(const PostArgs& p, int64_t row0, const double* x
   const auto X64 = gptr(uni(p.X64));
   const auto orig = gptr(uni(p.orig));
   const auto visited = gptr(uni(p.visited));
-  using out_t = typename std::conditional<OUT32, float, double>::type;
-  const auto mu = gptr((out_t*)uni(p.mu));
-  const auto var = gptr((out_t*)uni(p.var));
+  const bool out32 = uni(p.out32) != 0;
+  double* const mu = (double*)uni(p.mu);
+  double* const var = (double*)uni(p.var);
   const double mean_y = uni(p.st)->mean_y;
   const int64_t my_row = row0 + (l & 15);
   double xr[DM];
@@ -546,7 +550,11 @@ __device__ void post16_wave_reg(const PostArgs& p, int64_t row0, const double* x
   }
   double part = 0.0;
   int64_t cnt = 0;
-  if (l < 16 && my_row < n_valid) mu[my_row] = (out_t)(mean_y + mp);
+  if (l < 16 && my_row < n_valid) {
+    const double m = mean_y + mp;
+    if (out32) ((float*)mu)[my_row] = (float)m;
+    else mu[my_row] = m;
+  }
   if ((l & 15) == 0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -554,7 +562,8 @@ __device__ void post16_wave_reg(const PostArgs& p, int64_t row0, const double* x
       if (r < n_valid) {
         double v = amp - sq[i];
         v = v > 0.0 ? v : 0.0;
-        var[r] = (out_t)v;
+        if (out32) ((float*)var)[r] = (float)v;
+        else var[r] = v;
         if (!(visited && visited[orig[r]])) {
           part += v;
           ++cnt;
@@ -585,6 +594,7 @@ inline PostArgs make_post_args(const DevPtrs& P, const Layout& Lo, const GpConst
   PostArgs a{};
   a.n = n;
   a.n_pad = n_pad_of(n);
+  a.out32 = Lo.prec == BO_FP64 ? 0 : 1;
   a.ld = Lo.n_max_pad;
   a.d = Lo.d;
   a.nu2 = g.nu2;
