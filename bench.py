@@ -53,7 +53,7 @@ WORKLOADS = {
     "c1": dict(fn="config_c1", precision="fp64", dtype="fp64", peak="fp64",
                desc="1,536-point 8x8x6x4 grid, 144 invalid, n=20 observations, FP64 posterior"),
 }
-POSTERIOR_KERNEL = {"bf16x3": "k_post_bf16x3", "fp32": "k_post16", "fp64": "k_post16"}
+POSTERIOR_KERNEL = {"bf16x3": "k_post_bf16x3", "fp32": "k_post16r", "fp64": "k_post16r"}
 KERNEL_SOURCE = {"bf16x3": "paper_2111_14991_amd/csrc/k_bf16x3.hip", "fp32": "paper_2111_14991_amd/csrc/k_posterior.hip",
                  "fp64": "paper_2111_14991_amd/csrc/k_posterior.hip"}
 
@@ -569,8 +569,9 @@ def main() -> int:
         return bench_loop(args, torch, bo, W)
     wl = dict(WORKLOADS[args.workload])
     if args.precision and args.precision != wl["precision"]:
-        wl.update(precision=args.precision, dtype={"bf16x3": "bf16"}.get(args.precision, args.precision),
-                  peak={"bf16x3": "bf16"}.get(args.precision, args.precision),
+        # the FP64 and FP32 modes both take FP64 products
+        wl.update(precision=args.precision, dtype="bf16" if args.precision == "bf16x3" else "fp64",
+                  peak="bf16" if args.precision == "bf16x3" else "fp64",
                   desc=wl["desc"].rsplit(",", 1)[0] + f", {args.precision.upper()} posterior")
     s = getattr(W, wl["fn"])(0)
     dev = torch.device("cuda:0")
@@ -618,7 +619,8 @@ def main() -> int:
     achieved = flops / (post_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": traffic_from_profile(wl["precision"], args.workload),
-                "kernel": POSTERIOR_KERNEL[wl["precision"]], "kernel_ms": post_ms,
+                "kernel": POSTERIOR_KERNEL[wl["precision"]] + ("big" if wl["precision"] != "bf16x3" and n > 256 else ""),
+                "kernel_ms": post_ms,
                 "flops_per_launch": flops}
     fit_flops = 2.0 * n ** 3 / 3.0  # Cholesky n^3/3 + triangular inverse n^3/3, FP64
     if wl["precision"] == "bf16x3":

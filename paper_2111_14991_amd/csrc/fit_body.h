@@ -748,9 +748,8 @@ __device__ __forceinline__ double linv_at(const FitArgs& a, int row, int col) {
 
 // FP64 / FP32, 16x16x4 operand: fragment (J, t) at 2J(J+1) + t, t <= 4J+3;
 // lane l holds L^-1[16J + l%16][4t + l/16] (the transpose, as the B operand).
-// FP64 values for the FP64 mode and for every fit of n_pad <= kRegMax (whose
-// posterior takes FP64 products in both modes), FP32 values otherwise.
-__device__ __forceinline__ bool pack_f64(const FitArgs& a) { return a.prec == BO_FP64 || a.n_pad <= kRegMax; }
+// FP64 values: the posterior of both modes takes FP64 products.
+__device__ __forceinline__ bool pack_f64(const FitArgs& a) { return a.prec != BO_BF16X3; }
 
 __device__ void pack_elem16(const FitArgs& a, int64_t e) {
   const int64_t f = e >> 6;

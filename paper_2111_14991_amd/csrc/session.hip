@@ -300,11 +300,8 @@ size_t bpk_bytes(int prec, int n_pad) {
     const size_t M = n_pad / 64;  // pairs of 32-column blocks, 4(m+1) fragments per block
     return 4 * M * (M + 1) * 64 * 16 * 2;
   }
-  const size_t JB = n_pad / 16;
-  if (prec == BO_FP64) return 2 * JB * (JB + 1) * 64 * 8;
-  // FP32: FP64 values while n_pad <= kRegMax, FP32 values above
-  const size_t JR = std::min<size_t>(JB, kRegMax / 16);
-  return std::max(2 * JR * (JR + 1) * 64 * 8, 2 * JB * (JB + 1) * 64 * 4);
+  const size_t JB = n_pad / 16;  // FP64 values in both modes
+  return 2 * JB * (JB + 1) * 64 * 8;
 }
 
 bool make_layout(const bo_problem& p, Layout* L) {

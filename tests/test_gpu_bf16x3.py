@@ -5,7 +5,9 @@ parts (16 significant bits each value) and three products are accumulated in
 FP32, so each contraction term carries a relative error of about 2^-16 and the
 posterior variance an absolute error of a few 1e-5.  The tolerance TOL_B =
 2e-4 (normwise, same scale floors as the FP64/FP32 modes) is derived from that
-arithmetic; the measured errors are printed as the mode's error report.
+arithmetic; the measured errors are printed as the mode's error report.  The
+full-size step is also run in the FP64 mode against the same oracle step, at
+the 1e-6 bar of the FP64 and FP32 modes.
 """
 import numpy as np
 import pytest
@@ -17,6 +19,7 @@ from tests import parity as PR
 pytestmark = pytest.mark.gpu
 
 TOL_B = 2e-4
+TOL = 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -137,3 +140,27 @@ def test_bf16x3_full_size(bo):
     print(f"c3 chosen {list(r.idx)} oracle {list(ref.idx)}; agreement "
           f"{[int(a == b) for a, b in zip(r.idx, ref.idx)]}")
     S.close()
+    # the same step in the FP64 mode (register-resident posterior in column
+    # passes) against the same oracle step, at the 1e-6 bar
+    T = bo.Session(s.N, s.d, s.n, "fp64")
+    T.set_grid(s.levels, None, s.invalid)
+    T.fit(s.obs_idx[:n0], s.y[:n0])
+    var_s_64 = T.acquire(vis0, bo.AcqParams(mode=0)).var_mean
+    assert abs(var_s_64 - var_s_o) <= TOL * var_s_o
+    T.fit(s.obs_idx, s.y)
+    r64, vals64 = T.acquire_values(vis, bo.AcqParams(mode=1, mu_s=mu_s, var_s_mean=var_s_64))
+    assert r64.status == 0 and r64.n_unmasked == ref.n_unmasked
+    mu64, var64, _ = T.posterior(vis)
+    mu64, var64 = mu64.cpu().numpy(), var64.cpu().numpy()
+    A_64 = np.stack([v.cpu().numpy() for v in vals64], axis=1)
+    e_mu = _report("c3 fp64 mu", np.abs(mu64[keep] - ref.mu[keep]) / np.maximum(np.abs(ref.mu[keep]), ymax))
+    e_var = _report("c3 fp64 var", np.abs(var64[keep] - ref.var[keep]))
+    assert e_mu <= TOL and e_var <= TOL
+    assert abs(r64.var_mean - ref.var_mean) <= TOL * ref.var_mean
+    assert abs(r64.lam - ref.lam) <= TOL * ref.lam
+    for q, name in enumerate(("ei", "pi", "lcb")):
+        e = np.abs(A_64[keep, q] - A_r[keep, q]) / np.maximum(np.abs(A_r[keep, q]), scales[q])
+        assert _report(f"c3 fp64 {name}", e) <= TOL, name
+        assert PR.index_ok(int(r64.idx[q]), int(ref.idx[q]), A_r, q, mask, TOL, scales[q]), (q, r64.idx, ref.idx)
+    print(f"c3 fp64 chosen {list(r64.idx)} oracle {list(ref.idx)}")
+    T.close()

@@ -2,8 +2,8 @@
 
 - the kernel's per-candidate EI, PI and LCB (bo_acquire_values) against the
   oracle's, element by element (Section III-C);
-- the FP32 mode above 256 observations (the LDS-operand posterior with its
-  FP64 fallback rows) at n = 300 and 1000;
+- both modes above 256 observations (the register-resident posterior in
+  column passes) at n = 300 and 1000;
 - the sigma = 0 limits of the acquisitions (candidates that duplicate observed
   points, zero noise) and the far lower tail of EI and PI;
 - bo_observe: one evaluation per call, failures marked and never fitted
@@ -68,12 +68,13 @@ def test_acquisition_values(bo, precision, cfg):
     S.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
 @pytest.mark.parametrize("n", [300, 1000])
-def test_fp32_above_256_observations(bo, n):
+def test_above_256_observations(bo, n, precision):
     # 8,640 candidates of a 5-parameter grid, 20% restricted
     s = W.make_session(70 + n, (6, 6, 6, 5, 8), n, invalid_frac=0.2)
-    rep = _parity(bo, s, "fp32")
-    print(f"fp32 n={n}: " + ", ".join(f"{k} {rep[k]:.2e}" for k in ("mu", "var", "ei", "pi", "lcb")))
+    rep = _parity(bo, s, precision)
+    print(f"{precision} n={n}: " + ", ".join(f"{k} {rep[k]:.2e}" for k in ("mu", "var", "ei", "pi", "lcb")))
 
 
 def _dup_space(seed, n_obs=12, n_other=150, d=3):
