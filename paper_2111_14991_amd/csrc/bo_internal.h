@@ -84,7 +84,6 @@ struct DevPtrs {
   double* L;          // [n_max_pad^2]
   double* Dinv;       // [NB][32][32]
   double* Linv;       // [n_max_pad^2]
-  double* K0;         // [n_max_pad^2] amp * Matern between observations, no jitter (FP32 only)
   double* alpha;      // [n_max_pad]
   double* z;          // [n_max_pad]
   void* Bpk;          // packed L^-1 operand for the matrix cores
@@ -97,7 +96,7 @@ struct Layout {
   int d, n_max, n_max_pad, prec, w16;
   size_t off_st, off_res, off_X64, off_Xc16, off_orig, off_inv, off_blk, off_mu, off_var,
       off_vslots, off_aslots, off_Xo64, off_Xo16, off_y, off_A, off_L, off_Dinv, off_Linv,
-      off_alpha, off_z, off_Bpk, off_K0, off_obs, off_vis, total;
+      off_alpha, off_z, off_Bpk, off_obs, off_vis, total;
   int64_t n_vslots, n_aslots;
 };
 

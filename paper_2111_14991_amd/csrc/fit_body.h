@@ -30,7 +30,7 @@ constexpr int TT = 256;   // threads per team
 
 struct FitArgs {
   int n, n_pad, NB, d, nu2, tries, prec;
-  int ld;  // row stride of A, L, L^-1 and K0: n_pad of n_max, fixed for the session
+  int ld;  // row stride of A, L and L^-1: n_pad of n_max, fixed for the session
   double inv_l, amp, noise;
   const int64_t* obs_idx;
   const double* y_in;
@@ -45,7 +45,6 @@ struct FitArgs {
   double* L;
   double* Dinv;  // inverses of the diagonal tiles of L
   double* Linv;  // X = L^-1
-  double* K0;    // symmetric copy of amp * Matern without jitter, or null
   double* alpha;
   double* z;
   void* Bpk;
@@ -228,10 +227,6 @@ __device__ void op_build(const FitArgs& a, int ti, int tj, double delta, double*
       v = gi == gj ? 1.0 : 0.0;
     }
     a.A[tix(a, ti, tj, r, c)] = v;
-    if (a.K0) {
-      a.K0[(size_t)gi * a.ld + gj] = v0;
-      a.K0[(size_t)gj * a.ld + gi] = v0;
-    }
   }
   __syncthreads();
 }
@@ -920,7 +915,7 @@ __device__ __forceinline__ void fit_small_run(const FitArgs& a, unsigned char* s
 // new observation).  With k the covariances of the new point to the old ones,
 // l = L^-1 k and d^2 = amp + delta - |l|^2:
 //     L' = [L 0; l^T d],   L'^-1 = [L^-1 0; -(l^T L^-1) / d  1/d],
-// so only a new row of L, L^-1 (and of K0) is written, alpha is recomputed in
+// so only a new row of L and of L^-1 is written, alpha is recomputed in
 // O(n^2) and only the column blocks of the packed operand that hold row n0
 // are rewritten.  The new observation must already be at position n0 of
 // a.obs_idx / a.y_in.  When the current fit is not a valid fit of n0 points,
@@ -1010,18 +1005,13 @@ __device__ __forceinline__ void append_run(const FitArgs& a, unsigned char* s_ra
   }
   const double dg = sqrt(piv);
   const double inv_dg = 1.0 / dg;
-  // new rows: L[n0] = (l, d), L^-1[n0] = (-(l^T L^-1) / d, 1 / d), K0 row and column
+  // new rows: L[n0] = (l, d), L^-1[n0] = (-(l^T L^-1) / d, 1 / d)
   lt_cols_block(
       a, n0 + 1, n0, [&](int j) { return s_l[j]; },
       [&](int i, double w) {
         if (lane == 0) {
           a.L[(size_t)n0 * a.ld + i] = i < n0 ? s_l[i] : dg;
           a.Linv[(size_t)n0 * a.ld + i] = i < n0 ? -w * inv_dg : inv_dg;
-          if (a.K0) {
-            const double kv = i < n0 ? s_k[i] : a.amp;
-            a.K0[(size_t)n0 * a.ld + i] = kv;
-            a.K0[(size_t)i * a.ld + n0] = kv;
-          }
         }
       },
       wave, nwave, lane);
@@ -1096,7 +1086,6 @@ inline FitArgs make_args(const DevPtrs& P, const Layout& Lo, const GpConst& g, c
   a.L = P.L;
   a.Dinv = P.Dinv;
   a.Linv = P.Linv;
-  a.K0 = P.K0;
   a.alpha = P.alpha;
   a.z = P.z;
   a.Bpk = P.Bpk;

@@ -10,7 +10,6 @@ namespace bo {
 struct PostArgs {
   int n, n_pad, d, nu2;
   int out32;  // mean and variance stored in FP32 (the FP32 mode)
-  int ld;  // row stride of K0
   double inv_l, amp;
   int64_t n_valid, N_pad;
   const double* X64;
@@ -22,8 +21,6 @@ struct PostArgs {
   int w16;
   const double* alpha;
   const void* Bpk;
-  const double* K0;
-  const double* Linv;  // row stride ld
   void* mu;
   void* var;
   VarSlot* vslots;
@@ -392,7 +389,6 @@ inline PostArgs make_post_args(const DevPtrs& P, const Layout& Lo, const GpConst
   a.n = n;
   a.n_pad = n_pad_of(n);
   a.out32 = Lo.prec == BO_FP64 ? 0 : 1;
-  a.ld = Lo.n_max_pad;
   a.d = Lo.d;
   a.nu2 = g.nu2;
   a.inv_l = 1.0 / g.l;
@@ -408,8 +404,6 @@ inline PostArgs make_post_args(const DevPtrs& P, const Layout& Lo, const GpConst
   a.w16 = Lo.w16;
   a.alpha = P.alpha;
   a.Bpk = P.Bpk;
-  a.K0 = P.K0;
-  a.Linv = P.Linv;
   a.mu = P.mu;
   a.var = P.var;
   a.vslots = P.vslots;

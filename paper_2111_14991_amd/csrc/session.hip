@@ -347,7 +347,6 @@ bool make_layout(const bo_problem& p, Layout* L) {
   o.off_alpha = take(np * 8);
   o.off_z = take(np * 8);
   o.off_Bpk = take(bpk_bytes(p.precision, (int)np));
-  o.off_K0 = take(p.precision == BO_FP32 ? np * np * 8 : 0);
   o.off_obs = take(np * 8);
   o.off_vis = take(Np);
   o.total = off;
@@ -378,7 +377,6 @@ DevPtrs carve(const Layout& o, uint8_t* b) {
   P.alpha = (double*)(b + o.off_alpha);
   P.z = (double*)(b + o.off_z);
   P.Bpk = b + o.off_Bpk;
-  P.K0 = o.prec == BO_FP32 ? (double*)(b + o.off_K0) : nullptr;
   P.obs = (int64_t*)(b + o.off_obs);
   P.vis = b + o.off_vis;
   return P;
