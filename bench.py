@@ -37,7 +37,7 @@ MULTI = {
           "per step (fits, posterior slots, exploration factors, acquisition chunks, selections), "
           "autotuned work order and chunk size",
     "c5": "1024 live sessions (sizes as in c4, 10-200 initial observations), Poisson arrivals of step requests, "
-          "rank-1 append per request, 64 GB HBM admission budget, continuous batching over 3 launch streams",
+          "rank-1 append per request, 64 GB HBM admission budget, continuous batching",
     "loop": "tuning runs in simulation mode on the 102,060-point 8-parameter grid (25% restricted, 5% failing "
             "when run): maximin LHS initial sample of 20, 200 further evaluations, contextual variance, "
             "advanced multi acquisition (Table I settings)",
@@ -325,7 +325,11 @@ def _served_run(pool, rate, warm, count, rng, limit_s=120.0):
     t0 = time.perf_counter()
     t_next = t0
     pending = []  # arrival times waiting for an idle session
+    t_note = t0
     while done < total and time.perf_counter() - t0 < limit_s:
+        if time.perf_counter() - t_note > 20.0:
+            t_note = time.perf_counter()
+            _progress(f"{done} of {total} requests done")
         now = time.perf_counter()
         if rate is None:
             while pool.idle:
@@ -349,16 +353,23 @@ def _served_run(pool, rate, warm, count, rng, limit_s=120.0):
                 e2e.append(ms_e2e)
                 unm += u
     t_run = time.perf_counter() - (t_meas or t0)
+    # requests still in flight finish outside this point's statistics; under
+    # a budget that holds only some sessions, requests of waiting sessions
+    # cannot finish once no request retires a resident one: those are left
+    # to the server's close
+    t_drain = time.perf_counter() + 10.0
+    while pool.live and time.perf_counter() < t_drain:
+        pool.collect(1000)
     q = lambda v, p: float(np.percentile(v, p)) if v else None
     return {"requests": len(lat), "requests_per_s": len(lat) / t_run, "value": unm / t_run,
-            "complete": done >= total,
+            "complete": done >= total, "left_in_flight": len(pool.live),
             "latency_ms": {"p50": q(lat, 50), "p99": q(lat, 99), "mean": float(np.mean(lat)) if lat else None},
             "arrival_to_result_ms": {"p50": q(e2e, 50), "p99": q(e2e, 99)}}
 
 
 def bench_serving(args, torch, bo, W) -> int:
     """Serving form: 1,024 live sessions; the saturated request rate from a
-    closed-loop run, then Poisson arrivals at 0.5, 0.8, 0.95 and 1.1 times it
+    closed-loop run, then Poisson arrivals at 0.5, 0.6, 0.8, 0.95 and 1.1 times it
     (1,000 warm-up and --requests measured requests each) with a 64 GB
     admission budget, and one run at 0.8 times it with a 512 MB budget that
     forces admission; the plain per-session path (one step at a time, one
@@ -371,7 +382,7 @@ def bench_serving(args, torch, bo, W) -> int:
     t0 = time.perf_counter()
     spares = [(s, _objective_table(s)) for s in (W.c5_fresh_session(0, k) for k in range(320))]
     _progress(f"{len(spares)} replacement sessions drawn in {time.perf_counter() - t0:.1f} s")
-    srv = bo.Server(hbm_budget=64 << 30, max_batch=256, streams=3)
+    srv = bo.Server(hbm_budget=64 << 30, max_batch=args.max_batch, streams=args.streams)
     t0 = time.perf_counter()
     pool = _ServedPool(srv, bo, W, prec, rng, spares)
     t_open = time.perf_counter() - t0
@@ -379,14 +390,14 @@ def bench_serving(args, torch, bo, W) -> int:
     lam = sat["requests_per_s"]
     _progress(f"saturated: {lam:.0f} requests/s, p50 {sat['latency_ms']['p50']} ms")
     sweep = {}
-    for f in (0.5, 0.8, 0.95, 1.1):
+    for f in (0.5, 0.6, 0.8, 0.95, 1.1):
         sweep[str(f)] = dict(_served_run(pool, f * lam, warm, count, rng), rate_rps=f * lam)
         _progress(f"{f} x saturated: {sweep[str(f)]['requests']} requests, p99 {sweep[str(f)]['latency_ms']['p99']} ms")
     st = srv.stats()
     retired = pool.retired
     srv.close()
     # forced admission: the same sessions under a 512 MB budget
-    srv2 = bo.Server(hbm_budget=512 << 20, max_batch=256, streams=3)
+    srv2 = bo.Server(hbm_budget=512 << 20, max_batch=args.max_batch, streams=args.streams)
     pool2 = _ServedPool(srv2, bo, W, prec, np.random.Generator(np.random.PCG64(18)), spares)
     st2_open = srv2.stats()
     forced = dict(_served_run(pool2, 0.8 * lam, warm, count, rng), rate_rps=0.8 * lam,
@@ -431,7 +442,8 @@ def bench_serving(args, torch, bo, W) -> int:
         "n_gpus": 1, "steps": head["requests"], "warmup": warm,
         "ms_per_step": 1e3 / head["requests_per_s"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp64", "data": "synthetic",
-        "config": {"workload": "c5: " + MULTI["c5"] + f", {prec.upper()} posterior"
+        "config": {"workload": "c5: " + MULTI["c5"] + f" over {args.streams} launch streams of at most "
+                   f"{args.max_batch} requests, {prec.upper()} posterior"
                    + (" (FP64 products, FP32 results)" if prec == "fp32" else ""), "sessions": len(pool.slots),
                    "headline_rate": "0.8 x saturated", "open_s": t_open},
         "latency_ms": head["latency_ms"],
@@ -536,6 +548,8 @@ def main() -> int:
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS) + sorted(MULTI))
     ap.add_argument("--requests", type=int, default=10000,
                     help="c5: measured requests per arrival rate (after 1,000 warm-up requests)")
+    ap.add_argument("--streams", type=int, default=4, help="c5: the server's launch contexts")
+    ap.add_argument("--max-batch", type=int, default=128, help="c5: most requests in one launch")
     ap.add_argument("--precision", choices=["fp64", "fp32", "bf16x3"], default=None,
                     help="c1-c3: posterior arithmetic other than the workload's own")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")

@@ -517,7 +517,7 @@ class Server:
     requests are batched continuously by the library's scheduler thread."""
 
     def __init__(self, hbm_budget: int = 64 << 30, max_batch: int = 256, streams: int = 2,
-                 post_order: int = 0, acq_chunk: int = 8192, fit_order: int = 1):
+                 post_order: int = 0, acq_chunk: int = 2048, fit_order: int = 1):
         _torch()
         cfg = bo_server_config(int(hbm_budget), int(max_batch), int(streams),
                                bo_batch_config(post_order, acq_chunk, fit_order, 0))

@@ -657,12 +657,11 @@ __device__ void alpha_a_row(const FitArgs& a, int i, int lane) {
   if (lane == 0) a.alpha[i] = i < a.n ? v : 0.0;
 }
 
-// The same two products in one workgroup (n_pad <= 256): each wave takes
-// four of its rows (z) or columns (alpha) at a time and issues all their
-// loads before the first reduction, so a wave waits once per four rows
-// instead of once per row.  Every lane sums its terms in the order of
-// alpha_z_row / alpha_a_row and the reduction is the same, so the results
-// are the same bits.
+// z in one workgroup (n_pad <= 256): each wave takes four of its rows at a
+// time and issues all their loads before the first reduction, so a wave
+// waits once per four rows instead of once per row.  Every lane sums its
+// terms in the order of alpha_z_row and the reduction is the same, so the
+// results are the same bits.
 // out(i, sum_{j <= i} Linv[i][j] src(j)) for the rows i < ni of the wave
 // (zero for rows at or beyond nv), four at a time (z = L^-1 (y - m); also
 // L^-1 k in an append)
@@ -701,33 +700,26 @@ __device__ void l_rows_block(const FitArgs& a, int ni, int nv, Src src, Out out,
 // out(i, sum_{j >= i, j < nj} Linv[j][i] src(j)) for the columns i < ni of
 // the wave, four at a time (alpha = L^-T z; also the new row of L^-1 in an
 // append)
+// out(i, sum_{i <= j < nj} Linv[j][i] src(j)) for the columns i < ni <= 256
+// of L^-T src (alpha = L^-T z; also l^T L^-1 in an append), two threads per
+// column (a workgroup of 512): thread (i, h) sums the rows j = i + h, i + h + 2,
+// ... in ascending order, reading row j's entries of consecutive columns
+// together (coalesced); the odd rows' sum is then added to the even rows'.
+// s_part: 256 doubles of LDS.  The one-workgroup fit, the append and the
+// multi-workgroup fit's alpha (n_pad <= 256) all take this order, so their
+// alphas are the same bits.
 template <typename Src, typename Out>
-__device__ void lt_cols_block(const FitArgs& a, int ni, int nj, Src src, Out out, int wave, int NW, int lane) {
-  for (int i0 = wave; i0 < ni; i0 += 4 * NW) {
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int c = 0; c < kSmallFitMax / 64; ++c) {
-      double l[4], x[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + r * NW, j = i + 64 * c + lane;
-        const bool on = i < ni && j < nj;
-        l[r] = on ? a.Linv[(size_t)j * a.ld + i] : 0.0;
-        x[r] = on ? src(j) : 0.0;
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = i0 + r * NW, j = i + 64 * c + lane;
-        if (i < ni && j < nj) v[r] += l[r] * x[r];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      for (int off = 32; off > 0; off >>= 1) v[r] += shfl_xor_d(v[r], off);
-      const int i = i0 + r * NW;
-      if (i < ni) out(i, v[r]);
-    }
+__device__ void lt_cols_pair(const FitArgs& a, int ni, int nj, Src src, Out out, double* s_part) {
+  const int t = threadIdx.x, i = t & 255, h = t >> 8;
+  double v = 0.0;
+  if (i < ni) {
+#pragma unroll 8
+    for (int j = i + h; j < nj; j += 2) v += a.Linv[(size_t)j * a.ld + i] * src(j);
   }
+  if (h) s_part[i] = v;
+  __syncthreads();
+  if (!h && i < ni) out(i, v + s_part[i]);
+  __syncthreads();
 }
 
 // ---- packing of L^-1 for the matrix-core posterior kernels ----
@@ -890,12 +882,9 @@ __device__ __forceinline__ void fit_small_run(const FitArgs& a, unsigned char* s
       },
       wave, nwave, lane);
   __syncthreads();
-  lt_cols_block(
-      a, a.n_pad, a.n, [&](int j) { return a.z[j]; },
-      [&](int i, double v) {
-        if (lane == 0) a.alpha[i] = i < a.n ? v : 0.0;
-      },
-      wave, nwave, lane);
+  lt_cols_pair(
+      a, a.n_pad, a.n, [&](int j) { return a.z[j]; }, [&](int i, double v) { a.alpha[i] = i < a.n ? v : 0.0; },
+      s_red);
   int64_t nfrag;
   const int64_t ne = pack_count(a, &nfrag);
   for (int64_t e = threadIdx.x; e < ne; e += kSmallThreads) {
@@ -1006,15 +995,13 @@ __device__ __forceinline__ void append_run(const FitArgs& a, unsigned char* s_ra
   const double dg = sqrt(piv);
   const double inv_dg = 1.0 / dg;
   // new rows: L[n0] = (l, d), L^-1[n0] = (-(l^T L^-1) / d, 1 / d)
-  lt_cols_block(
+  lt_cols_pair(
       a, n0 + 1, n0, [&](int j) { return s_l[j]; },
       [&](int i, double w) {
-        if (lane == 0) {
-          a.L[(size_t)n0 * a.ld + i] = i < n0 ? s_l[i] : dg;
-          a.Linv[(size_t)n0 * a.ld + i] = i < n0 ? -w * inv_dg : inv_dg;
-        }
+        a.L[(size_t)n0 * a.ld + i] = i < n0 ? s_l[i] : dg;
+        a.Linv[(size_t)n0 * a.ld + i] = i < n0 ? -w * inv_dg : inv_dg;
       },
-      wave, nwave, lane);
+      s_red);
   // mean and incumbent over all observations, in the reduction order of fit_gather
   s_red[t] = t < a.n ? a.y[t] : 0.0;
   s_red[nt + t] = t < a.n ? a.y[t] : INFINITY;
@@ -1042,12 +1029,9 @@ __device__ __forceinline__ void append_run(const FitArgs& a, unsigned char* s_ra
       },
       wave, nwave, lane);
   __syncthreads();
-  lt_cols_block(
-      a, a.n_pad, a.n, [&](int j) { return a.z[j]; },
-      [&](int i, double v) {
-        if (lane == 0) a.alpha[i] = i < a.n ? v : 0.0;
-      },
-      wave, nwave, lane);
+  lt_cols_pair(
+      a, a.n_pad, a.n, [&](int j) { return a.z[j]; }, [&](int i, double v) { a.alpha[i] = i < a.n ? v : 0.0; },
+      s_red);
   // packed operand: the column blocks from the one holding row n0 on (the
   // fragment order does not depend on n for the 16x16x4 layout)
   const int J0 = n0 / 16, JB = a.n_pad / 16;

@@ -271,10 +271,20 @@ __global__ __launch_bounds__(TT) void k_fitL_zpack(FitArgs a) {
              (int64_t)gridDim.x * TT);
 }
 
-__global__ __launch_bounds__(TT) void k_fitL_alpha(FitArgs a) {
+// alpha = L^-T z: one wave per column; up to 256 observations one
+// workgroup of 512 in the one-workgroup fit's order (lt_cols_pair), so that
+// both fits give the same bits.
+__global__ __launch_bounds__(kAThreads) void k_fitL_alpha(FitArgs a) {
+  __shared__ double s_part[256];
   if (fit_stopped(a)) return;
-  const int i = blockIdx.x * (TT / 64) + (threadIdx.x >> 6);
-  if (i < a.n_pad) alpha_a_row(a, i, threadIdx.x & 63);
+  if (a.n_pad <= kSmallFitMax) {
+    lt_cols_pair(
+        a, a.n_pad, a.n, [&](int j) { return a.z[j]; }, [&](int i, double v) { a.alpha[i] = i < a.n ? v : 0.0; },
+        s_part);
+  } else {
+    const int i = blockIdx.x * (kAThreads / 64) + (threadIdx.x >> 6);
+    if (i < a.n_pad) alpha_a_row(a, i, threadIdx.x & 63);
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.st->jitter = jitter_of(a.noise, a.amp, 0);
     a.st->attempt = 0;
@@ -360,7 +370,15 @@ __global__ __launch_bounds__(kAThreads) void k_fitL(FitArgs a) {
   const int wave = (bid * kAThreads + tid) >> 6, nwave = G * (kAThreads / 64), lane = tid & 63;
   z_and_pack(a, wave, nwave, lane, (int64_t)bid * kAThreads + tid, (int64_t)G * kAThreads);
   if (!grid_sync(st, &bars, &s_ok)) return;
-  for (int i = wave; i < a.n_pad; i += nwave) alpha_a_row(a, i, lane);
+  if (a.n_pad <= kSmallFitMax) {
+    double* s_part = reinterpret_cast<double*>(s_raw);  // the tiles are free by now
+    if (bid == 0)
+      lt_cols_pair(
+          a, a.n_pad, a.n, [&](int j) { return a.z[j]; }, [&](int i, double v) { a.alpha[i] = i < a.n ? v : 0.0; },
+          s_part);
+  } else {
+    for (int i = wave; i < a.n_pad; i += nwave) alpha_a_row(a, i, lane);
+  }
   if (bid == 0 && tid == 0) {
     st->jitter = jitter_of(a.noise, a.amp, attempt);
     st->attempt = attempt;
@@ -451,7 +469,8 @@ hipError_t launch_fit_large(const DevPtrs& P, const Layout& Lo, const GpConst& g
     most = std::max(most, npanel + k + ntr + (k > 0 ? (m - 1) * k : 0));
   }
   hipLaunchKernelGGL(k_fitL_zpack, dim3(256), dim3(TT), 0, st, a);
-  hipLaunchKernelGGL(k_fitL_alpha, dim3(a.n_pad / (TT / 64)), dim3(TT), 0, st, a);
+  hipLaunchKernelGGL(k_fitL_alpha, dim3(a.n_pad <= kSmallFitMax ? 1 : a.n_pad / (kAThreads / 64)), dim3(kAThreads), 0,
+                     st, a);
   // the other attempts, on the device, when the first one failed
   if (resident < 2) return hipErrorInvalidConfiguration;
   const int G = std::max(2, std::min(most + 1, resident));

@@ -333,6 +333,15 @@ void retire(bo_server* srv) {
     L->tickets.clear();
     srv->cv_done.notify_all();
   }
+  // tickets taken by bo_server_wait stay in the completion queue until
+  // bo_server_wait_any passes them; keep the queue bounded for callers that
+  // never call it
+  if (srv->completed.size() > 2 * srv->reqs.size() + 4096) {
+    std::deque<uint64_t> keep;
+    for (uint64_t t : srv->completed)
+      if (srv->reqs.count(t)) keep.push_back(t);
+    srv->completed.swap(keep);
+  }
   // sessions being closed free their memory once idle
   for (auto it = srv->sessions.begin(); it != srv->sessions.end();) {
     SrvSession* ss = it->second.get();
