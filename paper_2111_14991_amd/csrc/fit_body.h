@@ -666,30 +666,32 @@ __device__ void alpha_a_row(const FitArgs& a, int i, int lane) {
 // (zero for rows at or beyond nv), four at a time (z = L^-1 (y - m); also
 // L^-1 k in an append)
 template <typename Src, typename Out>
-__device__ void l_rows_block(const FitArgs& a, int ni, int nv, Src src, Out out, int wave, int NW, int lane) {
-  for (int i0 = wave; i0 < ni; i0 += 4 * NW) {
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
+__device__ __forceinline__ void l_rows_block(const FitArgs& a, int ni, int nv, Src src, Out out, int wave, int NW, int lane) {
+  constexpr int R = 4;  // rows of a wave in flight together
+  for (int i0 = wave; i0 < ni; i0 += R * NW) {
+    double v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = 0.0;
 #pragma unroll
     for (int c = 0; c < kSmallFitMax / 64; ++c) {
       const int j = 64 * c + lane;
       if (64 * c < ni) {
-        double l[4], x[4];
+        const double x = j < nv ? src(j) : 0.0;
+        double l[R];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < R; ++r) {
           const int i = i0 + r * NW;
-          const bool on = i < nv && j <= i;
-          l[r] = on ? a.Linv[(size_t)i * a.ld + j] : 0.0;
-          x[r] = on ? src(j) : 0.0;
+          l[r] = (i < nv && j <= i) ? a.Linv[(size_t)i * a.ld + j] : 0.0;
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < R; ++r) {
           const int i = i0 + r * NW;
-          if (i < nv && j <= i) v[r] += l[r] * x[r];
+          if (i < nv && j <= i) v[r] += l[r] * x;
         }
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < R; ++r) {
       for (int off = 32; off > 0; off >>= 1) v[r] += shfl_xor_d(v[r], off);
       const int i = i0 + r * NW;
       if (i < ni) out(i, v[r]);
@@ -697,9 +699,6 @@ __device__ void l_rows_block(const FitArgs& a, int ni, int nv, Src src, Out out,
   }
 }
 
-// out(i, sum_{j >= i, j < nj} Linv[j][i] src(j)) for the columns i < ni of
-// the wave, four at a time (alpha = L^-T z; also the new row of L^-1 in an
-// append)
 // out(i, sum_{i <= j < nj} Linv[j][i] src(j)) for the columns i < ni <= 256
 // of L^-T src (alpha = L^-T z; also l^T L^-1 in an append), two threads per
 // column (a workgroup of 512): thread (i, h) sums the rows j = i + h, i + h + 2,
@@ -709,7 +708,7 @@ __device__ void l_rows_block(const FitArgs& a, int ni, int nv, Src src, Out out,
 // multi-workgroup fit's alpha (n_pad <= 256) all take this order, so their
 // alphas are the same bits.
 template <typename Src, typename Out>
-__device__ void lt_cols_pair(const FitArgs& a, int ni, int nj, Src src, Out out, double* s_part) {
+__device__ __forceinline__ void lt_cols_pair(const FitArgs& a, int ni, int nj, Src src, Out out, double* s_part) {
   const int t = threadIdx.x, i = t & 255, h = t >> 8;
   double v = 0.0;
   if (i < ni) {
