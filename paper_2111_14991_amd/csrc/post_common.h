@@ -336,9 +336,10 @@ struct BigWave {
   }
 };
 
-// PW: blocks per full pass (the register budget: 16 with DM = 8, 14 with more
-// coordinates).
-template <int DM, int PW = (DM <= 8 ? 16 : 14)>
+// PW: blocks per full pass.  With 16, the accumulators and the coordinates
+// leave a few registers to reload once per phase, which still beats 14-block
+// passes (fewer regenerated k-steps).
+template <int DM, int PW = 16>
 __device__ void post16_wave_big(const PostArgs& p, int64_t row0, const double* xs, const double* as,
                                 double* part_out, int64_t* cnt_out) {
   static_assert(DM <= kMaxD && PW >= 1 && PW <= 16, "shape");
