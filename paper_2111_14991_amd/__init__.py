@@ -429,7 +429,7 @@ def bo_step_noalloc(X, obs_idx, y, precision="fp64", invalid=None, visited=None,
 
 
 class Batch:
-    """Many sessions stepped together by one persistent, graph-captured launch
+    """Many sessions stepped together by one captured graph of kernels
     (bo_batch_*).  The sessions must outlive the batch."""
 
     def __init__(self, sessions: Sequence[Session], device=None, stream=None):

@@ -1,5 +1,5 @@
 """Batched form (bo_batch_*): many sessions of uneven candidate counts,
-dimensions and observation counts in one persistent, graph-captured launch.
+dimensions and observation counts in one captured graph of kernels.
 
 Each session's result must be, bit for bit, the one the single-session path
 gives on the same inputs (the same kernels per candidate, and the mean
