@@ -174,3 +174,34 @@ def test_server_errors(bo):
     r, _ = srv.wait(srv.submit(sid, int(s.obs_idx[10]), float(s.y[10]), True, acq))
     assert r.status == 0 and r.n_obs == 11
     srv.close()
+
+
+def test_server_close_while_setting_up(bo):
+    # sessions are set up by the server's setup thread; one closed right after
+    # it was opened (typically before its setup ends) refuses requests and
+    # returns its memory, and the others are not affected
+    pop = [W.make_session(60 + i, (6, 5, 5, 4), 40, invalid_frac=0.2) for i in range(3)]
+    srv = bo.Server(hbm_budget=8 << 30, max_batch=4, streams=2)
+    n0 = 12
+    sids = [srv.open(s.levels, s.obs_idx[:n0], s.y[:n0], N=s.N, cand=s.cand, invalid=s.invalid, n_max=64,
+                     precision="fp64") for s in pop]
+    srv.close_session(sids[0])
+    acq = bo.AcqParams(mode=0, lambda_const=0.01)
+    with pytest.raises(bo.BOError):
+        srv.submit(sids[0], int(pop[0].obs_idx[n0]), float(pop[0].y[n0]), True, acq)
+    for i in (1, 2):
+        s = pop[i]
+        r, _ = srv.wait(srv.submit(sids[i], int(s.obs_idx[n0]), float(s.y[n0]), True, acq))
+        a = Alone(bo, s, "fp64", n0)
+        _same(r, a.step(int(s.obs_idx[n0]), float(s.y[n0]), True, acq))
+        a.S.close()
+    b = bo.server_session_bytes(pop[0].N, pop[0].d, 64, "fp64")
+    import time
+    t_end = time.time() + 10.0
+    while time.time() < t_end:
+        st = srv.stats()
+        if st["sessions_resident"] == 2 and st["bytes_in_use"] == 2 * b:
+            break
+        time.sleep(0.01)
+    assert st["sessions_resident"] == 2 and st["bytes_in_use"] == 2 * b, st
+    srv.close()
