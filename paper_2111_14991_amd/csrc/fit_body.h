@@ -699,6 +699,50 @@ __device__ __forceinline__ void l_rows_block(const FitArgs& a, int ni, int nv, S
   }
 }
 
+// l_rows_block for two source vectors at once over the same rows (one pass
+// over L^-1); each product is summed as l_rows_block sums it.
+template <typename Src1, typename Src2, typename Out>
+__device__ __forceinline__ void l_rows_block2(const FitArgs& a, int ni, int nv, Src1 src1, Src2 src2, Out out,
+                                              int wave, int NW, int lane) {
+  constexpr int R = 4;
+  for (int i0 = wave; i0 < ni; i0 += R * NW) {
+    double v[R], u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = u[r] = 0.0;
+#pragma unroll
+    for (int c = 0; c < kSmallFitMax / 64; ++c) {
+      const int j = 64 * c + lane;
+      if (64 * c < ni) {
+        const double x = j < nv ? src1(j) : 0.0;
+        const double y = j < nv ? src2(j) : 0.0;
+        double l[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = i0 + r * NW;
+          l[r] = (i < nv && j <= i) ? a.Linv[(size_t)i * a.ld + j] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = i0 + r * NW;
+          if (i < nv && j <= i) {
+            v[r] += l[r] * x;
+            u[r] += l[r] * y;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      for (int off = 32; off > 0; off >>= 1) {
+        v[r] += shfl_xor_d(v[r], off);
+        u[r] += shfl_xor_d(u[r], off);
+      }
+      const int i = i0 + r * NW;
+      if (i < ni) out(i, v[r], u[r]);
+    }
+  }
+}
+
 // out(i, sum_{i <= j < nj} Linv[j][i] src(j)) for the columns i < ni <= 256
 // of L^-T src (alpha = L^-T z; also l^T L^-1 in an append), two threads per
 // column (a workgroup of 512): thread (i, h) sums the rows j = i + h, i + h + 2,
@@ -968,11 +1012,29 @@ __device__ __forceinline__ void append_run(const FitArgs& a, unsigned char* s_ra
     s_k[i] = a.amp * matern64(a.nu2, sqrt(s2), a.inv_l);
   }
   __syncthreads();
-  // l = L^-1 k
-  l_rows_block(
-      a, n0, n0, [&](int j) { return s_k[j]; },
-      [&](int i, double v) {
-        if (lane == 0) s_l[i] = v;
+  // mean and incumbent over all observations, in the reduction order of fit_gather
+  s_red[t] = t < a.n ? a.y[t] : 0.0;
+  s_red[nt + t] = t < a.n ? a.y[t] : INFINITY;
+  __syncthreads();
+  for (int off = nt / 2; off > 0; off >>= 1) {
+    if (t < off) {
+      s_red[t] += s_red[t + off];
+      s_red[nt + t] = fmin(s_red[nt + t], s_red[nt + t + off]);
+    }
+    __syncthreads();
+  }
+  const double m = s_red[0] / (double)a.n;
+  const double fb = s_red[nt];
+  __syncthreads();
+  // one pass over the old rows of L^-1: l = L^-1 k and the old rows of
+  // z = L^-1 (y - m) (rows < n0 keep their entries in the new factor)
+  l_rows_block2(
+      a, n0, n0, [&](int j) { return s_k[j]; }, [&](int j) { return a.y[j] - m; },
+      [&](int i, double v, double u) {
+        if (lane == 0) {
+          s_l[i] = v;
+          a.z[i] = u;
+        }
       },
       wave, nwave, lane);
   __syncthreads();
@@ -1001,32 +1063,27 @@ __device__ __forceinline__ void append_run(const FitArgs& a, unsigned char* s_ra
         a.Linv[(size_t)n0 * a.ld + i] = i < n0 ? -w * inv_dg : inv_dg;
       },
       s_red);
-  // mean and incumbent over all observations, in the reduction order of fit_gather
-  s_red[t] = t < a.n ? a.y[t] : 0.0;
-  s_red[nt + t] = t < a.n ? a.y[t] : INFINITY;
-  __syncthreads();
-  for (int off = nt / 2; off > 0; off >>= 1) {
-    if (t < off) {
-      s_red[t] += s_red[t + off];
-      s_red[nt + t] = fmin(s_red[nt + t], s_red[nt + t + off]);
-    }
-    __syncthreads();
-  }
-  const double m = s_red[0] / (double)a.n;
   if (t == 0) {
     st->n = a.n;
     st->mean_y = m;
-    st->f_best = s_red[nt];
+    st->f_best = fb;
     st->min_piv = fmin(st->min_piv, piv);
   }
   __threadfence_block();
   __syncthreads();
-  l_rows_block(
-      a, a.n_pad, a.n, [&](int j) { return a.y[j] - m; },
-      [&](int i, double v) {
-        if (lane == 0) a.z[i] = v;
-      },
-      wave, nwave, lane);
+  // z's new row, each lane's terms and the reduction in the order of
+  // l_rows_block, and zeros past it
+  if (wave == 0) {
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < kSmallFitMax / 64; ++c) {
+      const int j = 64 * c + lane;
+      if (j <= n0) v += a.Linv[(size_t)n0 * a.ld + j] * (a.y[j] - m);
+    }
+    for (int off = 32; off > 0; off >>= 1) v += shfl_xor_d(v, off);
+    if (lane == 0) a.z[n0] = v;
+  }
+  if (t > n0 && t < a.n_pad) a.z[t] = 0.0;
   __syncthreads();
   lt_cols_pair(
       a, a.n_pad, a.n, [&](int j) { return a.z[j]; }, [&](int i, double v) { a.alpha[i] = i < a.n ? v : 0.0; },
