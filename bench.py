@@ -17,8 +17,10 @@ every GPU result against that oracle step.
 from __future__ import annotations
 
 import argparse
+import collections
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -248,6 +250,21 @@ def _objective_table(s):
     return s.landscape.value(s.grid_index(np.arange(s.N)))
 
 
+class _Draws:
+    """A stream of pre-drawn variates (one generator call per block), so that
+    the load generator's own cost per request stays small."""
+
+    def __init__(self, draw, block=1 << 16):
+        self.draw, self.block = draw, block
+        self.buf, self.k = draw(block).tolist(), 0
+
+    def __call__(self):
+        if self.k == len(self.buf):
+            self.buf, self.k = self.draw(self.block).tolist(), 0
+        self.k += 1
+        return self.buf[self.k - 1]
+
+
 class _ServedPool:
     """The serving form's live sessions on one server: each has at most one
     request in flight (BO is sequential), evaluates the EI choice of its last
@@ -256,16 +273,22 @@ class _ServedPool:
 
     RETIRE = 220
 
-    def __init__(self, srv, bo, W, prec, rng, spares, seed=0, sessions=1024):
+    def __init__(self, srv, bo, W, prec, rng, spares, population, seed=0):
         self.srv, self.bo, self.W, self.prec, self.rng, self.seed = srv, bo, W, prec, rng, seed
         self.spares = spares
         self.fresh = 0
-        self.slots = []
-        for s in W.config_c5_population(seed, sessions):
-            self.slots.append(self._open(s, _objective_table(s)))
+        self.noise = _Draws(lambda k: rng.standard_normal(k))
+        self.slots = [self._open(s, f) for s, f in population]
         self.idle = list(range(len(self.slots)))
         self.live = {}
         self.retired = 0
+
+    def wait_setup(self, limit_s=120.0):
+        """Waits until the server has set up every admitted session."""
+        t0 = time.perf_counter()
+        while self.srv.stats()["sessions_setting_up"] and time.perf_counter() - t0 < limit_s:
+            time.sleep(0.01)
+        return time.perf_counter() - t0
 
     def _open(self, s, f):
         sid = self.srv.open(s.levels, s.obs_idx, s.y, N=s.N, cand=s.cand, invalid=s.invalid, n_max=256,
@@ -273,7 +296,8 @@ class _ServedPool:
         vis = s.visited().astype(bool)
         pool = np.flatnonzero((s.invalid == 0) & ~vis)
         acq = self.bo.AcqParams(mode=1, mu_s=float(np.mean(s.y[:s.n_init])), var_s_mean=0.0)
-        return {"s": s, "f": f, "sid": sid, "vis": vis, "n": s.n, "next": int(self.rng.choice(pool)), "acq": acq}
+        return {"s": s, "f": f, "sid": sid, "vis": vis, "n": s.n, "next": int(self.rng.choice(pool)),
+                "acq": acq.c()}
 
     def _replacement(self):
         k = self.fresh
@@ -283,11 +307,18 @@ class _ServedPool:
         s = self.W.c5_fresh_session(self.seed, k)
         return s, _objective_table(s)
 
+    def take_idle(self, u):
+        """Removes and returns the idle session at uniform position u in [0, 1)."""
+        idle = self.idle
+        k = int(u * len(idle))
+        idle[k], idle[-1] = idle[-1], idle[k]
+        return idle.pop()
+
     def submit(self, i, t_arrive):
         c = self.slots[i]
         idx = c["next"]
         # the run-time measurement: the objective with its lognormal noise
-        y = float(c["f"][idx] * np.exp(0.02 * self.rng.standard_normal()))
+        y = c["f"].item(idx) * math.exp(0.02 * self.noise())
         c["vis"][idx] = True
         c["n"] += 1
         self.live[self.srv.submit(c["sid"], idx, y, True, c["acq"])] = (i, t_arrive)
@@ -297,13 +328,13 @@ class _ServedPool:
         timeout_us for the first): [(latency from submission ms, latency from
         arrival ms, n_unmasked)]."""
         out = []
-        got = self.srv.wait_any(1024, int(timeout_us))
+        got = self.srv.wait_any(1024, int(timeout_us), raw=True)
         now = time.perf_counter()
         for t, r, ms in got:
             i, t_arrive = self.live.pop(t)
             assert r.status == 0, r.status
             c = self.slots[i]
-            c["next"] = int(r.idx[0])
+            c["next"] = r.idx[0]
             out.append((ms, (now - t_arrive) * 1e3, r.n_unmasked))
             if c["n"] >= self.RETIRE:
                 self.srv.close_session(c["sid"])
@@ -318,13 +349,17 @@ def _served_run(pool, rate, warm, count, rng, limit_s=120.0):
     seconds); rate None: closed loop (every idle session submits at once: the
     saturated rate), else Poisson arrivals at `rate` requests/s, each to a
     uniformly random idle session (an arrival with no idle session waits for
-    one).  Statistics over the finished requests after the first `warm`."""
+    one).  Statistics over the finished requests after the first `warm`; the
+    mean number of requests inside the server (rate x mean latency) shows
+    whether the server or this load generator set the pace."""
     done, lat, e2e, unm = 0, [], [], 0
     t_meas = None
     total = warm + count
+    uni = _Draws(lambda k: rng.random(k))
+    gap = _Draws(lambda k: rng.exponential(1.0 / rate, k)) if rate else None
     t0 = time.perf_counter()
     t_next = t0
-    pending = []  # arrival times waiting for an idle session
+    pending = collections.deque()  # arrival times waiting for an idle session
     t_note = t0
     while done < total and time.perf_counter() - t0 < limit_s:
         if time.perf_counter() - t_note > 20.0:
@@ -333,15 +368,13 @@ def _served_run(pool, rate, warm, count, rng, limit_s=120.0):
         now = time.perf_counter()
         if rate is None:
             while pool.idle:
-                i = pool.idle.pop(int(rng.integers(0, len(pool.idle))))
-                pool.submit(i, now)
+                pool.submit(pool.take_idle(uni()), now)
         else:
             while now >= t_next:
                 pending.append(t_next)
-                t_next += float(rng.exponential(1.0 / rate))
+                t_next += gap()
             while pending and pool.idle:
-                i = pool.idle.pop(int(rng.integers(0, len(pool.idle))))
-                pool.submit(i, pending.pop(0))
+                pool.submit(pool.take_idle(uni()), pending.popleft())
         # wait for a completion until the next arrival is due, at most 200 us
         wait_us = 200 if rate is None else max(0.0, min(t_next - time.perf_counter(), 2e-4)) * 1e6
         for ms, ms_e2e, u in pool.collect(wait_us):
@@ -361,10 +394,12 @@ def _served_run(pool, rate, warm, count, rng, limit_s=120.0):
     while pool.live and time.perf_counter() < t_drain:
         pool.collect(1000)
     q = lambda v, p: float(np.percentile(v, p)) if v else None
-    return {"requests": len(lat), "requests_per_s": len(lat) / t_run, "value": unm / t_run,
+    rps = len(lat) / t_run
+    return {"requests": len(lat), "requests_per_s": rps, "value": unm / t_run,
             "complete": done >= total, "left_in_flight": len(pool.live),
             "latency_ms": {"p50": q(lat, 50), "p99": q(lat, 99), "mean": float(np.mean(lat)) if lat else None},
-            "arrival_to_result_ms": {"p50": q(e2e, 50), "p99": q(e2e, 99)}}
+            "arrival_to_result_ms": {"p50": q(e2e, 50), "p99": q(e2e, 99)},
+            "in_server_mean": rps * float(np.mean(lat)) * 1e-3 if lat else None}
 
 
 def bench_serving(args, torch, bo, W) -> int:
@@ -373,40 +408,53 @@ def bench_serving(args, torch, bo, W) -> int:
     (1,000 warm-up and --requests measured requests each) with a 64 GB
     admission budget, and one run at 0.8 times it with a 512 MB budget that
     forces admission; the plain per-session path (one step at a time, one
-    stream, same precision) beside it."""
+    stream, same precision) beside it.  Every run starts from the same 1,024
+    sessions on a fresh server (every request adds an observation, so a
+    population left from an earlier run would cost more per request than the
+    one the saturated rate was measured on)."""
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     prec = args.precision or "fp32"
     rng = np.random.Generator(np.random.PCG64(17))
     warm, count = 1000, int(args.requests)
     t0 = time.perf_counter()
+    pop = W.config_c5_population(0, 1024)
+    population = [(s, _objective_table(s)) for s in pop]
     spares = [(s, _objective_table(s)) for s in (W.c5_fresh_session(0, k) for k in range(320))]
-    _progress(f"{len(spares)} replacement sessions drawn in {time.perf_counter() - t0:.1f} s")
-    srv = bo.Server(hbm_budget=64 << 30, max_batch=args.max_batch, streams=args.streams)
-    t0 = time.perf_counter()
-    pool = _ServedPool(srv, bo, W, prec, rng, spares)
-    t_open = time.perf_counter() - t0
-    sat = _served_run(pool, None, warm, count, rng)
+    _progress(f"{len(population)} sessions and {len(spares)} replacements drawn in {time.perf_counter() - t0:.1f} s")
+
+    def fresh(budget):
+        srv = bo.Server(hbm_budget=budget, max_batch=args.max_batch, streams=args.streams)
+        t0 = time.perf_counter()
+        pool = _ServedPool(srv, bo, W, prec, np.random.Generator(np.random.PCG64(18)), spares, population)
+        pool.wait_setup()
+        return srv, pool, time.perf_counter() - t0
+
+    def finish(srv, pool, res):
+        st = srv.stats()
+        srv.close()
+        res["mean_batch"] = st["mean_batch"]
+        res["sessions_retired_and_replaced"] = pool.retired
+        return res
+
+    srv, pool, t_open = fresh(64 << 30)
+    sat = finish(srv, pool, _served_run(pool, None, warm, count, rng))
     lam = sat["requests_per_s"]
     _progress(f"saturated: {lam:.0f} requests/s, p50 {sat['latency_ms']['p50']} ms")
     sweep = {}
     for f in (0.5, 0.6, 0.8, 0.95, 1.1):
-        sweep[str(f)] = dict(_served_run(pool, f * lam, warm, count, rng), rate_rps=f * lam)
-        _progress(f"{f} x saturated: {sweep[str(f)]['requests']} requests, p99 {sweep[str(f)]['latency_ms']['p99']} ms")
-    st = srv.stats()
-    retired = pool.retired
-    srv.close()
+        srv, pool, _ = fresh(64 << 30)
+        sweep[str(f)] = finish(srv, pool, dict(_served_run(pool, f * lam, warm, count, rng), rate_rps=f * lam))
+        _progress(f"{f} x saturated: {sweep[str(f)]['requests']} requests, p50 {sweep[str(f)]['latency_ms']['p50']} "
+                  f"ms, p99 {sweep[str(f)]['latency_ms']['p99']} ms")
     # forced admission: the same sessions under a 512 MB budget
-    srv2 = bo.Server(hbm_budget=512 << 20, max_batch=args.max_batch, streams=args.streams)
-    pool2 = _ServedPool(srv2, bo, W, prec, np.random.Generator(np.random.PCG64(18)), spares)
+    srv2, pool2, _ = fresh(512 << 20)
     st2_open = srv2.stats()
-    forced = dict(_served_run(pool2, 0.8 * lam, warm, count, rng), rate_rps=0.8 * lam,
-                  sessions_resident_at_open=st2_open["sessions_resident"],
-                  sessions_waiting_at_open=st2_open["sessions_waiting"])
-    srv2.close()
+    forced = finish(srv2, pool2, dict(_served_run(pool2, 0.8 * lam, warm, count, rng), rate_rps=0.8 * lam,
+                                      sessions_resident_at_open=st2_open["sessions_resident"],
+                                      sessions_waiting_at_open=st2_open["sessions_waiting"]))
     _progress(f"forced admission: {forced['requests']} requests, complete {forced['complete']}")
     # the plain per-session path on the first 64 sessions, one request at a time
-    pop = W.config_c5_population(0)
     acqs = [bo.AcqParams(mode=1, mu_s=float(np.mean(s.y[:s.n_init])), var_s_mean=0.0) for s in pop[:64]]
     P = []
     for s in pop[:64]:
@@ -450,8 +498,6 @@ def bench_serving(args, torch, bo, W) -> int:
         "saturated": sat,
         "sweep": sweep,
         "forced_admission_512MB": forced,
-        "sessions_retired_and_replaced": retired,
-        "server": st,
         "plain_path": {"requests": len(plat), "value": punm / t_plain, "requests_per_s": len(plat) / t_plain,
                        "latency_ms": {"p50": float(np.percentile(plat, 50)), "p99": float(np.percentile(plat, 99))}},
         "roofline": None,

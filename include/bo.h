@@ -374,6 +374,7 @@ typedef struct {
   int64_t pending;           /* requests not yet launched */
   size_t bytes_in_use;
   double mean_batch;         /* requests per launch */
+  int64_t sessions_setting_up; /* admitted, being uploaded and fitted (counted as resident too) */
 } bo_server_info;
 
 /* Device bytes one session of this problem holds while resident. */

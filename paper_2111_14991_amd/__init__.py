@@ -70,7 +70,7 @@ class bo_server_config(C.Structure):
 class bo_server_info(C.Structure):
     _fields_ = [("steps_done", C.c_int64), ("launches", C.c_int64), ("sessions_resident", C.c_int64),
                 ("sessions_waiting", C.c_int64), ("pending", C.c_int64), ("bytes_in_use", C.c_size_t),
-                ("mean_batch", C.c_double)]
+                ("mean_batch", C.c_double), ("sessions_setting_up", C.c_int64)]
 
 
 class BOError(RuntimeError):
@@ -559,8 +559,10 @@ class Server:
     def close_session(self, sid: int):
         _check(lib().bo_server_close(self.h, int(sid)), "bo_server_close")
 
-    def submit(self, sid: int, idx: int, y: float, valid: bool = True, acq: Optional[AcqParams] = None) -> int:
-        a = (acq or AcqParams(mode=0)).c()
+    def submit(self, sid: int, idx: int, y: float, valid: bool = True, acq=None) -> int:
+        """acq: AcqParams, or its C form (AcqParams.c()) to convert once for
+        many requests."""
+        a = acq if isinstance(acq, bo_acq_params) else (acq or AcqParams(mode=0)).c()
         t = C.c_uint64()
         _check(lib().bo_server_submit(self.h, int(sid), int(idx), float(y), 1 if valid else 0, C.byref(a),
                                       C.byref(t)), "bo_server_submit")
@@ -578,9 +580,11 @@ class Server:
         _check(lib().bo_server_wait(self.h, C.c_uint64(ticket), C.byref(r), C.byref(ms)), "bo_server_wait")
         return _result(r), ms.value
 
-    def wait_any(self, max_count: int = 256, timeout_us: int = 1000) -> list:
+    def wait_any(self, max_count: int = 256, timeout_us: int = 1000, raw: bool = False) -> list:
         """Finished requests not yet returned, in completion order (waits up
-        to timeout_us for the first): [(ticket, StepResult, latency_ms)]."""
+        to timeout_us for the first): [(ticket, StepResult, latency_ms)].
+        raw: the results as bo_acq_result structures that stay valid until
+        the next wait_any call (no conversion)."""
         if getattr(self, "_cq", None) is None or self._cq[0] < max_count:
             self._cq = (max_count, (C.c_uint64 * max_count)(), (bo_acq_result * max_count)(),
                         (C.c_double * max_count)())
@@ -588,7 +592,8 @@ class Server:
         k = C.c_int32()
         _check(lib().bo_server_wait_any(self.h, int(max_count), int(timeout_us), t, r, ms, C.byref(k)),
                "bo_server_wait_any")
-        return [(int(t[i]), _result(r[i]), float(ms[i])) for i in range(k.value)]
+        conv = (lambda x: x) if raw else _result
+        return [(t[i], conv(r[i]), ms[i]) for i in range(k.value)]
 
     def stats(self) -> dict:
         i = bo_server_info()

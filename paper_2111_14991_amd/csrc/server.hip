@@ -695,6 +695,7 @@ bo_status bo_server_stats(bo_server* srv, bo_server_info* out) {
   for (auto& kv : srv->sessions) {
     if (kv.second->state == 1 || kv.second->state == 2 || kv.second->state == 4) ++s.sessions_resident;
     else if (kv.second->state == 0) ++s.sessions_waiting;
+    if (kv.second->state == 4) ++s.sessions_setting_up;
   }
   s.pending = (int64_t)srv->pending.size();
   *out = s;
