@@ -434,6 +434,8 @@ def bench_serving(args, torch, bo, W) -> int:
         st = srv.stats()
         srv.close()
         res["mean_batch"] = st["mean_batch"]
+        res["server_us"] = {"wait_to_launch": st["mean_wait_us"], "launch_call": st["mean_launch_us"],
+                            "graph_on_device": st["mean_gpu_us"]}
         res["sessions_retired_and_replaced"] = pool.retired
         return res
 

@@ -375,6 +375,9 @@ typedef struct {
   size_t bytes_in_use;
   double mean_batch;         /* requests per launch */
   int64_t sessions_setting_up; /* admitted, being uploaded and fitted (counted as resident too) */
+  double mean_wait_us;       /* per request: submission to the start of its launch call */
+  double mean_launch_us;     /* per launch: host time of the launch call */
+  double mean_gpu_us;        /* per launch: device time of the batched step graph */
 } bo_server_info;
 
 /* Device bytes one session of this problem holds while resident. */

@@ -70,7 +70,8 @@ class bo_server_config(C.Structure):
 class bo_server_info(C.Structure):
     _fields_ = [("steps_done", C.c_int64), ("launches", C.c_int64), ("sessions_resident", C.c_int64),
                 ("sessions_waiting", C.c_int64), ("pending", C.c_int64), ("bytes_in_use", C.c_size_t),
-                ("mean_batch", C.c_double), ("sessions_setting_up", C.c_int64)]
+                ("mean_batch", C.c_double), ("sessions_setting_up", C.c_int64),
+                ("mean_wait_us", C.c_double), ("mean_launch_us", C.c_double), ("mean_gpu_us", C.c_double)]
 
 
 class BOError(RuntimeError):

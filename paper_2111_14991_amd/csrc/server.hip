@@ -19,6 +19,7 @@
 //  - Latency is measured from submission to the moment the scheduler has the
 //    result.
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <chrono>
@@ -73,7 +74,7 @@ struct Request {
   double y = 0.0;
   int32_t valid = 1;
   AcqArgs acq{};
-  Clock::time_point t_submit, t_done;
+  Clock::time_point t_submit, t_launch, t_done;
   bo_acq_result res{};
   bool done = false;
   int32_t n_new = 0;
@@ -123,6 +124,10 @@ struct bo_server {
   std::thread worker;
   std::thread setup_worker;
   int64_t steps_done = 0, n_launches = 0, items_launched = 0;
+  // latency decomposition: submission to launch call (summed over requests),
+  // host time of the launch calls, device time of the launches
+  double wait_s = 0.0, launch_s = 0.0, gpu_ms = 0.0;
+  int64_t gpu_timed = 0;
 };
 
 namespace {
@@ -305,7 +310,12 @@ void retire(bo_server* srv) {
     if (!L->busy || !L->ctx.done()) continue;
     const int cnt = (int)L->tickets.size();
     L->out.resize(cnt);
-    const bo_status rc = L->ctx.finish(L->out.data(), nullptr);
+    float ms = -1.f;
+    const bo_status rc = L->ctx.finish(L->out.data(), &ms);
+    if (ms >= 0.f) {
+      srv->gpu_ms += ms;
+      ++srv->gpu_timed;
+    }
     const auto now = Clock::now();
     for (int i = 0; i < cnt; ++i) {
       Request& r = srv->reqs[L->tickets[i]];
@@ -314,6 +324,7 @@ void retire(bo_server* srv) {
       if (rc != BO_OK) r.res.status = rc;
       r.done = true;
       r.t_done = now;
+      srv->wait_s += std::chrono::duration<double>(r.t_launch - r.t_submit).count();
       srv->completed.push_back(L->tickets[i]);
       ss->busy = false;
       const int32_t st = r.res.status;
@@ -415,7 +426,10 @@ void dispatch(bo_server* srv) {
       it = srv->pending.erase(it);
     }
     if (L->items.empty()) return;
+    const auto t0 = Clock::now();
+    for (uint64_t t : L->tickets) srv->reqs[t].t_launch = t0;
     const bo_status rc = L->ctx.launch(L->items.data(), (int)L->items.size(), srv->cfg.tiles);
+    srv->launch_s += std::chrono::duration<double>(Clock::now() - t0).count();
     if (rc != BO_OK) {
       for (uint64_t t : L->tickets) fail_request(srv, t, rc);
       L->tickets.clear();
@@ -431,6 +445,9 @@ void dispatch(bo_server* srv) {
 
 void worker_main(bo_server* srv) {
   (void)hipSetDevice(srv->device);
+  // the completion polls below are short timed waits: without this, the
+  // kernel's default timer slack (50 us) would stretch each one to ~70 us
+  (void)prctl(PR_SET_TIMERSLACK, 1UL, 0UL, 0UL, 0UL);
   std::unique_lock<std::mutex> lk(srv->mu);
   for (;;) {
     retire(srv);
@@ -449,7 +466,7 @@ void worker_main(bo_server* srv) {
     for (auto& L : srv->launches) inflight |= L->busy;
     if (inflight) {
       // poll the launches' completion events between wake-ups
-      srv->cv_work.wait_for(lk, std::chrono::microseconds(20));
+      srv->cv_work.wait_for(lk, std::chrono::microseconds(10));
     } else if (!srv->stop) {
       srv->cv_work.wait(lk);
     }
@@ -508,6 +525,7 @@ bo_status bo_server_create(bo_server** out, const bo_server_config* cfg) {
   for (int i = 0; i < cfg->streams; ++i) {
     std::unique_ptr<Launch> L(new Launch());
     bo_status rc = L->ctx.init(cfg->max_batch, (unsigned char*)srv->ctx_mem + per * i, per, srv->launch_streams[i]);
+    if (rc == BO_OK) rc = L->ctx.set_timing(1);
     if (rc != BO_OK) {
       L->ctx.destroy();
       undo();
@@ -697,6 +715,9 @@ bo_status bo_server_stats(bo_server* srv, bo_server_info* out) {
     else if (kv.second->state == 0) ++s.sessions_waiting;
     if (kv.second->state == 4) ++s.sessions_setting_up;
   }
+  s.mean_wait_us = srv->steps_done ? 1e6 * srv->wait_s / (double)srv->steps_done : 0.0;
+  s.mean_launch_us = srv->n_launches ? 1e6 * srv->launch_s / (double)srv->n_launches : 0.0;
+  s.mean_gpu_us = srv->gpu_timed ? 1e3 * srv->gpu_ms / (double)srv->gpu_timed : 0.0;
   s.pending = (int64_t)srv->pending.size();
   *out = s;
   return BO_OK;
