@@ -11,13 +11,19 @@ template <bool F32>
 __global__ __launch_bounds__(kAcqThreads) void k_acquire(AcqKArgs a) {
   __shared__ Best s_best[kAcqThreads / 64];
   __shared__ int s_nan[kAcqThreads / 64];
-  __shared__ int s_last;
   const int64_t per = (a.n_valid + gridDim.x - 1) / gridDim.x;
   const int64_t c0 = (int64_t)blockIdx.x * per;
   const int64_t c1 = c0 + per < a.n_valid ? c0 + per : a.n_valid;
   acq_range<F32>(a, c0, c1, &a.slots[blockIdx.x], s_best, s_nan);
-  if (!last_block(&a.st->ticket_acq, &s_last)) return;
-  acq_finish(a, gridDim.x, s_best, s_nan);
+}
+
+// The step result from the slots (one workgroup, after the acquisition
+// launch: a last-workgroup ticket would need a device-scope fence in every
+// workgroup of it).
+__global__ __launch_bounds__(kAcqThreads) void k_acquire_finish(AcqKArgs a, int nslots) {
+  __shared__ Best s_best[kAcqThreads / 64];
+  __shared__ int s_nan[kAcqThreads / 64];
+  acq_finish(a, nslots, s_best, s_nan);
 }
 
 // Posterior written back in the caller's enumeration (NaN where excluded).
@@ -45,7 +51,7 @@ __global__ void k_scatter_post(int64_t N, const int32_t* inv_map, const uint8_t*
 }  // namespace
 
 // Workgroups of one acquisition launch: kAcqPerThread candidates per thread,
-// at most kAcqMaxBlocks (each publishes a slot behind a device-scope fence).
+// at most kAcqMaxBlocks (the slots of the session's workspace).
 int64_t acquire_blocks(int64_t n_valid) {
   const int64_t per = (int64_t)kAcqThreads * kAcqPerThread;
   const int64_t g = (n_valid + per - 1) / per;
@@ -64,6 +70,9 @@ hipError_t launch_acquire(const DevPtrs& P, const Layout& Lo, int64_t n_valid, c
     hipLaunchKernelGGL(k_acquire<false>, dim3(grid), dim3(kAcqThreads), 0, st, a);
   else
     hipLaunchKernelGGL(k_acquire<true>, dim3(grid), dim3(kAcqThreads), 0, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_acquire_finish, dim3(1), dim3(kAcqThreads), 0, st, a, grid);
   return hipGetLastError();
 }
 

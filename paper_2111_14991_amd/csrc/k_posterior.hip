@@ -3,8 +3,8 @@
 // register-resident FP64 accumulators (post16_wave_reg up to 256
 // observations, post16_wave_big in column passes above); a workgroup of four
 // waves publishes the sum and count of variances over its not-yet-evaluated
-// candidates in its slot; the last workgroup reduces the slots in order to the
-// mean variance and the exploration factor of Section III-F.
+// candidates in its slot; a one-workgroup launch after it reduces the slots in
+// order to the mean variance and the exploration factor of Section III-F.
 #include "bo_internal.h"
 #include "bo_device.h"
 #include "post_common.h"
@@ -19,9 +19,6 @@ template <int JB, int DM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_post16r(PostArgs p) {
   __shared__ double s_wsum[4];
   __shared__ int64_t s_wcnt[4];
-  __shared__ double s_rsum[256];
-  __shared__ int64_t s_rcnt[256];
-  __shared__ int s_last;
   __shared__ double s_xo[16 * JB * kObsPitch];
   __shared__ double s_alpha[16 * JB];
   if (p.st->status != BO_OK) return;
@@ -46,7 +43,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     p.vslots[blockIdx.x].sum = s;
     p.vslots[blockIdx.x].count = c;
   }
-  if (last_block(&p.st->ticket_post, &s_last)) finish_lambda(p, gridDim.x, s_rsum, s_rcnt, blockDim.x);
+}
+
+// Mean variance and exploration factor from the slots (one workgroup, after
+// the posterior launch: a last-workgroup ticket in the posterior would need a
+// device-scope fence in every one of its workgroups).
+__global__ __launch_bounds__(256) void k_post_lambda(PostArgs p, int nslots) {
+  __shared__ double s_rsum[256];
+  __shared__ int64_t s_rcnt[256];
+  if (p.st->status != BO_OK) return;
+  finish_lambda(p, nslots, s_rsum, s_rcnt, 256);
 }
 
 template <int JB>
@@ -69,9 +75,6 @@ __global__ __launch_bounds__(kBigThreads) void k_post16big(PostArgs p) {
   extern __shared__ __align__(16) double s_obs[];
   __shared__ double s_wsum[8];
   __shared__ int64_t s_wcnt[8];
-  __shared__ double s_rsum[256];
-  __shared__ int64_t s_rcnt[256];
-  __shared__ int s_last;
   if (p.st->status != BO_OK) return;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int rows = 16 * reg_jb(p.n);
@@ -103,8 +106,6 @@ __global__ __launch_bounds__(kBigThreads) void k_post16big(PostArgs p) {
       p.vslots[slot].count = c;
     }
   }
-  if (last_block(&p.st->ticket_post, &s_last))
-    finish_lambda(p, (int)(nslots > 0 ? nslots : 1), s_rsum, s_rcnt, 256);
 }
 
 hipError_t launch_post_bf16x3(const PostArgs& a, hipStream_t st);
@@ -133,17 +134,20 @@ hipError_t launch_posterior(const DevPtrs& P, const Layout& Lo, const GpConst& g
       hipLaunchKernelGGL(k_post16big<8>, dim3(gbig), dim3(kBigThreads), lds, st, a);
     else
       hipLaunchKernelGGL(k_post16big<kMaxD>, dim3(gbig), dim3(kBigThreads), lds, st, a);
-    return hipGetLastError();
-  }
-  switch (reg_jb(a.n)) {
+  } else {
+    switch (reg_jb(a.n)) {
 #define BO_REG_CASE(J) \
   case J: launch_post16r<J>(a, grid, st); break;
-    BO_REG_CASE(1) BO_REG_CASE(2) BO_REG_CASE(3) BO_REG_CASE(4) BO_REG_CASE(5) BO_REG_CASE(6)
-    BO_REG_CASE(7) BO_REG_CASE(8) BO_REG_CASE(9) BO_REG_CASE(10) BO_REG_CASE(11) BO_REG_CASE(12)
-    BO_REG_CASE(13) BO_REG_CASE(14) BO_REG_CASE(15) BO_REG_CASE(16)
+      BO_REG_CASE(1) BO_REG_CASE(2) BO_REG_CASE(3) BO_REG_CASE(4) BO_REG_CASE(5) BO_REG_CASE(6)
+      BO_REG_CASE(7) BO_REG_CASE(8) BO_REG_CASE(9) BO_REG_CASE(10) BO_REG_CASE(11) BO_REG_CASE(12)
+      BO_REG_CASE(13) BO_REG_CASE(14) BO_REG_CASE(15) BO_REG_CASE(16)
 #undef BO_REG_CASE
-    default: return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_post_lambda, dim3(1), dim3(256), 0, st, a, grid);
   return hipGetLastError();
 }
 
