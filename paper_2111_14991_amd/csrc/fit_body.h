@@ -676,7 +676,10 @@ __device__ __forceinline__ void l_rows_block(const FitArgs& a, int ni, int nv, S
     for (int c = 0; c < kSmallFitMax / 64; ++c) {
       const int j = 64 * c + lane;
       if (64 * c < ni) {
-        const double x = j < nv ? src(j) : 0.0;
+        // the source at a clamped index (a load behind a branch is waited
+        // for before the branch joins)
+        const double xv = src(j < nv ? j : nv - 1);
+        const double x = j < nv ? xv : 0.0;
         double l[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -713,8 +716,12 @@ __device__ __forceinline__ void l_rows_block2(const FitArgs& a, int ni, int nv, 
     for (int c = 0; c < kSmallFitMax / 64; ++c) {
       const int j = 64 * c + lane;
       if (64 * c < ni) {
-        const double x = j < nv ? src1(j) : 0.0;
-        const double y = j < nv ? src2(j) : 0.0;
+        // the sources at a clamped index, so that their loads sit behind no
+        // branch (a load behind one is waited for before the branch joins)
+        const int jc = j < nv ? j : nv - 1;
+        const double xv = src1(jc), yv = src2(jc);
+        const double x = j < nv ? xv : 0.0;
+        const double y = j < nv ? yv : 0.0;
         double l[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
