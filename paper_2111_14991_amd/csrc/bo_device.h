@@ -152,6 +152,27 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
   return __shfl_xor(v, m, 64);
 }
 
+// Sum of v over each row of 16 lanes, in every lane of the row: DPP moves
+// only (quad permutations for lane distances 1 and 2, row rotations by 4 and
+// 8), where a butterfly of lane exchanges would wait on the LDS crossbar at
+// every step.
+__device__ __forceinline__ double row_sum16_d(double v) {
+  v += __builtin_amdgcn_update_dpp(0.0, v, 0xB1, 0xf, 0xf, true);   // quad_perm [1,0,3,2]
+  v += __builtin_amdgcn_update_dpp(0.0, v, 0x4E, 0xf, 0xf, true);   // quad_perm [2,3,0,1]
+  v += __builtin_amdgcn_update_dpp(0.0, v, 0x124, 0xf, 0xf, true);  // row_ror:4
+  v += __builtin_amdgcn_update_dpp(0.0, v, 0x128, 0xf, 0xf, true);  // row_ror:8
+  return v;
+}
+
+// Sum of v over the 64 lanes of the wave, in every lane: the row sums, then
+// two lane exchanges across the rows.
+__device__ __forceinline__ double wave_sum_d(double v) {
+  v = row_sum16_d(v);
+  v += shfl_xor_d(v, 16);
+  v += shfl_xor_d(v, 32);
+  return v;
+}
+
 // A wave-uniform value the compiler cannot prove uniform (read through a
 // pointer chosen at run time, or passed to a called function) moved to
 // scalar registers: each 32-bit word is taken from the first active lane.

@@ -646,14 +646,14 @@ __device__ void alpha_z_row(const FitArgs& a, int i, double m, int lane) {
   if (i < a.n)
 #pragma unroll 4
     for (int j = lane; j <= i; j += 64) v += a.Linv[(size_t)i * a.ld + j] * (a.y[j] - m);
-  for (int off = 32; off > 0; off >>= 1) v += shfl_xor_d(v, off);
+  v = wave_sum_d(v);
   if (lane == 0) a.z[i] = v;
 }
 __device__ void alpha_a_row(const FitArgs& a, int i, int lane) {
   double v = 0.0;
 #pragma unroll 4
   for (int j = i + lane; j < a.n; j += 64) v += a.Linv[(size_t)j * a.ld + i] * a.z[j];
-  for (int off = 32; off > 0; off >>= 1) v += shfl_xor_d(v, off);
+  v = wave_sum_d(v);
   if (lane == 0) a.alpha[i] = i < a.n ? v : 0.0;
 }
 
@@ -694,16 +694,19 @@ __device__ __forceinline__ void l_rows_block(const FitArgs& a, int ni, int nv, S
       }
     }
 #pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = wave_sum_d(v[r]);
+#pragma unroll
     for (int r = 0; r < R; ++r) {
-      for (int off = 32; off > 0; off >>= 1) v[r] += shfl_xor_d(v[r], off);
       const int i = i0 + r * NW;
       if (i < ni) out(i, v[r]);
     }
   }
 }
 
+
 // l_rows_block for two source vectors at once over the same rows (one pass
-// over L^-1); each product is summed as l_rows_block sums it.
+// over L^-1); each lane sums its products as l_rows_block does, and the lane
+// partials are added by wave_sum_d.
 template <typename Src1, typename Src2, typename Out>
 __device__ __forceinline__ void l_rows_block2(const FitArgs& a, int ni, int nv, Src1 src1, Src2 src2, Out out,
                                               int wave, int NW, int lane) {
@@ -738,12 +741,14 @@ __device__ __forceinline__ void l_rows_block2(const FitArgs& a, int ni, int nv, 
         }
       }
     }
+    // the eight wave sums first (independent chains), then the outputs
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      for (int off = 32; off > 0; off >>= 1) {
-        v[r] += shfl_xor_d(v[r], off);
-        u[r] += shfl_xor_d(u[r], off);
-      }
+      v[r] = wave_sum_d(v[r]);
+      u[r] = wave_sum_d(u[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
       const int i = i0 + r * NW;
       if (i < ni) out(i, v[r], u[r]);
     }
@@ -1087,7 +1092,7 @@ __device__ __forceinline__ void append_run(const FitArgs& a, unsigned char* s_ra
       const int j = 64 * c + lane;
       if (j <= n0) v += a.Linv[(size_t)n0 * a.ld + j] * (a.y[j] - m);
     }
-    for (int off = 32; off > 0; off >>= 1) v += shfl_xor_d(v, off);
+    v = wave_sum_d(v);
     if (lane == 0) a.z[n0] = v;
   }
   if (t > n0 && t < a.n_pad) a.z[t] = 0.0;

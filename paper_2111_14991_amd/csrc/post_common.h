@@ -134,14 +134,7 @@ __device__ __forceinline__ void post16_store(const PostArgs& p, int64_t row0, do
   mp += shfl_xor_d(mp, 16);
   mp += shfl_xor_d(mp, 32);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    double v = sq[i];
-    v += shfl_xor_d(v, 1);
-    v += shfl_xor_d(v, 2);
-    v += shfl_xor_d(v, 4);
-    v += shfl_xor_d(v, 8);
-    sq[i] = v;
-  }
+  for (int i = 0; i < 4; ++i) sq[i] = row_sum16_d(sq[i]);
   double part = 0.0;
   int64_t cnt = 0;
   if (l < 16 && my_row < n_valid) {
