@@ -1,5 +1,5 @@
 // Shared by the posterior kernels: launch arguments, the per-wave posterior of
-// the FP64 / FP32 modes, and the last-workgroup reduction of the mean variance
+// the FP64 / FP32 modes, and the reduction of the slots to the mean variance
 // and the exploration factor.
 #pragma once
 #include "bo_internal.h"
