@@ -99,6 +99,7 @@ __device__ __forceinline__ void load_dinv(Tile& s, const FitArgs& a, int k, int 
 // ---- phase 0: gather observations, validate, prior mean and incumbent ----
 // Runs in one workgroup (n <= 1024); s_red holds 2 * blockDim.x doubles and
 // s_pos 1024 ints.
+template <bool COORDS = true>
 __device__ void fit_gather(const FitArgs& a, double* s_red, int* s_pos, int* s_bad) {
   const int t = threadIdx.x, nt = blockDim.x;
   if (t == 0) *s_bad = 0;
@@ -141,8 +142,9 @@ __device__ void fit_gather(const FitArgs& a, double* s_red, int* s_pos, int* s_b
   }
   __syncthreads();
   // coordinates: one observation per thread, its kMaxD loads issued
-  // together (one round for n_pad <= blockDim.x)
-  for (int i = t; i < a.n_pad; i += nt) {
+  // together (one round for n_pad <= blockDim.x); with COORDS false other
+  // workgroups take them (gather_coords_row)
+  for (int i = t; COORDS && i < a.n_pad; i += nt) {
     const bool live = i < a.n;
     const int pos = live ? s_pos[i] : 0;
     double x[kMaxD];
@@ -179,6 +181,26 @@ __device__ void fit_gather(const FitArgs& a, double* s_red, int* s_pos, int* s_b
     st->fail_at = 0xffffffffu;
   }
   __syncthreads();
+}
+
+// The coordinate part of fit_gather for observation i alone, with the same
+// values: its row of X in Xo64 (zeros past d and past n) and its augmented
+// FP16 row for the BF16X3 distance products; an index the gather refuses
+// reads row 0, as there.
+__device__ __forceinline__ void gather_coords_row(const FitArgs& a, int i) {
+  const bool live = i < a.n;
+  int pos = 0;
+  if (live) {
+    const int64_t idx = a.obs_idx[i];
+    const int p = (idx >= 0 && idx < a.N) ? a.inv_map[idx] : -1;
+    pos = (p < 0 || !isfinite(a.y_in[i])) ? 0 : p;
+  }
+  double x[kMaxD];
+#pragma unroll
+  for (int j = 0; j < kMaxD; ++j) x[j] = (live && j < a.d) ? a.X64[(int64_t)j * a.N_pad + pos] : 0.0;
+#pragma unroll
+  for (int j = 0; j < kMaxD; ++j) a.Xo64[(size_t)i * kMaxD + j] = x[j];
+  if (a.Xo16) aug16_row(x, a.d, true, a.Xo16 + (size_t)i * 2 * a.w16, a.w16);
 }
 
 // ---- tile operations (one team; thread tt = 64 w + lane owns rows

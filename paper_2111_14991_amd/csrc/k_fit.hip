@@ -18,11 +18,20 @@ __global__ __launch_bounds__(kSmallThreads) void k_append(FitArgs a) {
 }
 
 // ======================= large fit: one launch per phase ==================
+// Workgroup 0: observations, their mean and incumbent, the index check and
+// the fit state; workgroup b >= 1: the coordinates of observations
+// 64 (b - 1) .. 64 b - 1, one per thread of its first wave (the augmented
+// rows of the BF16X3 form are long enough to be worth spreading).
 __global__ __launch_bounds__(1024) void k_fitL_gather(FitArgs a) {
   __shared__ double s_red[2 * 1024];
   __shared__ int s_pos[kMaxN];
   __shared__ int s_flag;
-  fit_gather(a, s_red, s_pos, &s_flag);
+  if (blockIdx.x == 0) {
+    fit_gather<false>(a, s_red, s_pos, &s_flag);
+    return;
+  }
+  const int i = ((int)blockIdx.x - 1) * 64 + (int)threadIdx.x;
+  if (threadIdx.x < 64 && i < a.n_pad) gather_coords_row(a, i);
 }
 
 constexpr int kAThreads = 2 * TT;
@@ -455,7 +464,7 @@ hipError_t launch_fit_large(const DevPtrs& P, const Layout& Lo, const GpConst& g
   const int NB = a.NB;
   const size_t lds = 4 * sizeof(Tile);
   int most = 0;
-  hipLaunchKernelGGL(k_fitL_gather, dim3(1), dim3(1024), 0, st, a);
+  hipLaunchKernelGGL(k_fitL_gather, dim3(1 + a.n_pad / 64), dim3(1024), 0, st, a);
   // first attempt
   hipLaunchKernelGGL(k_fitL_build, dim3(NB * (NB + 1) / 2), dim3(TT), 0, st, a);
   for (int k = 0; k < NB; ++k) {
